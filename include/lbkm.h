@@ -1,0 +1,220 @@
+/*
+ * lbkm.h -- C ABI of the MI355X (gfx950) implementation of the two-dimensional
+ * multiple-relaxation-time lattice Boltzmann kinetic model for combustion
+ * (Xu, Lin, Zhang, Li, arXiv:1411.6697).
+ *
+ * One time step advances the 24 discrete distribution functions f_i of the
+ * D2V24 model and the reaction progress lambda on a cell-centred Nx x Ny grid:
+ *
+ *   f_i^{n+1} = f_i^n + dt [ -v_i . grad_NND f_i
+ *                            - M^-1_il ( R_l (f_hat_l - f_hat^eq_l) - A_hat_l )
+ *                            + C_i ]                       (Sec. II, Eq. Boltzmann_chemical)
+ *   lambda^{n+1} = lambda^n + dlambda_chem - dt u . grad_NND lambda
+ *                                                           (Sec. II, Eq. lambda_equation)
+ *
+ * with f_hat = M f (rows m_1..m_24 of Sec. II), f_hat^eq the 24 closed forms of
+ * Sec. II (entries 14 and 16 carry the factor T that Eq. moment7 requires),
+ * A_hat_8, A_hat_9 of Eqs. ArtificialA8/ArtificialA9 entering with the
+ * moment-space sign of Eq. CE_LB, C_i of Eq. C_i with F = dlambda_chem / dt,
+ * the Cochran rate integrated exactly over the step with p frozen, and the NND
+ * scheme (Zhang 1988, flux-split minmod) upwinded by the sign of v_i (of u for
+ * lambda).  Time integration is forward Euler.  Delta_k = f_hat_k - f_hat^eq_k
+ * (Sec. VI) with Delta_1..4 = 0.
+ *
+ * Conventions
+ *  - Every function returns lbkm_status; no exception crosses the ABI.  A
+ *    human-readable message for the last failure on a context is available
+ *    from lbkm_last_error (valid until the next call on that context).
+ *  - All field pointers are DEVICE pointers to float64 data unless stated
+ *    otherwise.  The caller owns every field and state buffer and keeps it
+ *    alive while bound; the library never frees them.  The library owns only
+ *    its constant tables and reduction scratch (freed by lbkm_destroy).
+ *  - Layouts: a scalar field is [ny][nx] dense (row pitch nx) unless a
+ *    pitch is given.  The distribution buffers are structure-of-arrays
+ *    f[24][ny][pitch] with pitch >= nx, velocity i = 8 g + d in group
+ *    g = 0 (v_a), 1 (v_b), 2 (v_c) and unit direction d of
+ *    (1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).  lambda buffers
+ *    are [ny][pitch].
+ *  - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *    stream).  Functions that return values in host memory synchronise that
+ *    stream; all others are asynchronous.
+ *  - A context is not thread-safe; calls on one context must be serialised.
+ */
+#ifndef LBKM_H
+#define LBKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbkm_ctx lbkm_ctx;
+
+typedef enum {
+    LBKM_OK = 0,
+    LBKM_EINVAL = -1,      /* invalid argument or parameter                         */
+    LBKM_ESINGULAR = -2,   /* moment matrix M singular or too ill-conditioned       */
+    LBKM_ENOMEM = -3,      /* device or host allocation failed                      */
+    LBKM_EDEVICE = -4,     /* HIP runtime error (message holds the HIP error string) */
+    LBKM_ESTATE = -5,      /* call out of order (e.g. step before set_params)       */
+    LBKM_ENONFINITE = -6   /* lbkm_check found NaN/Inf, rho <= 0 or T <= 0          */
+} lbkm_status;
+
+typedef enum { LBKM_BC_PERIODIC = 0, LBKM_BC_OUTFLOW = 1 } lbkm_bc;
+
+/* D2V24 velocity model (Sec. II): group speeds and internal-dof parameters. */
+typedef struct { double va, vb, vc, eta_a, eta_b, eta_c; } lbkm_dvm;
+
+/* Grid and time step.  Ghost cells are implicit: periodic wrap, or
+ * zero-gradient outflow (both ghosts copy the edge cell). */
+typedef struct {
+    int32_t nx, ny;
+    double dx, dy, dt;
+    int32_t bc_x, bc_y;           /* lbkm_bc */
+    lbkm_dvm dvm;
+} lbkm_grid;
+
+/* Cochran rate of Eq. lambda_equation: d lambda/dt = omega1 p^m (1-lambda)
+ * + omega2 p^n lambda (1-lambda), active only where T > T_ig. */
+typedef struct { double omega1, omega2, m, n, T_ig; } lbkm_rates;
+
+/* ---- single-grid context ------------------------------------------------ */
+
+/* Create a context for one grid; validates the grid and the velocity model and
+ * builds M and its block inverse on the host (LBKM_ESINGULAR if M is singular
+ * or its condition number exceeds 1e12).  hip_stream is a hipStream_t or NULL.
+ * No device work happens here (device tables are allocated by lbkm_bind_buffers).
+ * On failure *out may still hold a context for lbkm_last_error; destroy it. */
+lbkm_status lbkm_create(const lbkm_grid* grid, void* hip_stream, lbkm_ctx** out);
+
+/* Bind caller-owned device buffers: f_a, f_b of 24*ny*pitch doubles and
+ * lam_a, lam_b of ny*pitch doubles (pitch >= nx elements).  The state lives in
+ * the "a" buffers after init_fields/set_state and ping-pongs between a and b. */
+lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b,
+                              double* lam_a, double* lam_b, int64_t pitch);
+
+/* Relaxation rates and physics (Sec. II-III).  S holds R_1..R_24 (host array).
+ * gamma = (D+I+2)/(D+I) gives I = 2/(gamma-1) - 2 (snapped to the nearest
+ * integer when within 1e-9).  If Pr > 0 the library requires R_5 = R_6 = R_7
+ * and sets R_8 = R_9 = Pr R_5 (Pr = R_kappa / R_mu, Sec. III); if Pr <= 0, S is
+ * used as given.  Q is the heat release (Eq. chemical_energy).
+ * LBKM_EINVAL if gamma <= 1 or I <= 0, any R_k <= 0, R_k dt >= 2 for k >= 5,
+ * T_ig < 0, m or n < 0, omega1 or omega2 < 0, or a non-finite value. */
+lbkm_status lbkm_set_params(lbkm_ctx* ctx, const double S[24], double gamma, double Pr,
+                            double Q, const lbkm_rates* rates);
+
+/* Initial state f = M^-1 f_hat^eq(rho, u, T) and lambda (Eq. moment12).  Inputs are
+ * dense [ny][nx] device arrays.  LBKM_EINVAL is not raised for rho <= 0 or T <= 0
+ * in the data (that would need a device sync); lbkm_check reports them. */
+lbkm_status lbkm_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
+                             const double* uy, const double* T, const double* lambda);
+
+/* Advance n >= 0 time steps (asynchronous). */
+lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n);
+
+/* Macroscopic readout rho, u_x, u_y, T, p = rho T, lambda into dense [ny][nx]
+ * device arrays; any pointer may be NULL (asynchronous). */
+lbkm_status lbkm_get_moments(lbkm_ctx* ctx, double* rho, double* ux, double* uy,
+                             double* T, double* p, double* lambda);
+
+/* TNE readout (Sec. VI): delta[20][ny][nx] holds Delta_5..Delta_24 and d[ny][nx]
+ * holds sqrt(sum_k Delta_k^2); either may be NULL (asynchronous). */
+lbkm_status lbkm_get_tne(lbkm_ctx* ctx, double* delta, double* d);
+
+/* Deterministic grid reductions into host memory (synchronises):
+ * out[0..7] = sum rho, sum rho u_x, sum rho u_y, sum E (E = f_hat_4 / 2, total energy
+ * density), sum_cells sum_k Delta_k^2, (dx/ny) sum |Delta_5| (row-averaged global TNE
+ * area, Sec. VI B), min lambda, max lambda. */
+lbkm_status lbkm_reduce(lbkm_ctx* ctx, double out[8]);
+
+/* Health check (synchronises): LBKM_ENONFINITE if any cell holds NaN/Inf in f or
+ * lambda, rho <= 0 or T <= 0; LBKM_OK otherwise. */
+lbkm_status lbkm_check(lbkm_ctx* ctx);
+
+/* Copy the current state out to / in from caller device buffers f[24][ny][nx]
+ * and lam[ny][nx] (dense, asynchronous).  set_state marks the fields as set. */
+lbkm_status lbkm_get_state(lbkm_ctx* ctx, double* f, double* lam);
+lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam);
+
+/* Host copies of the dense 24x24 moment matrix M (row k = moment m_{k+1}, column i =
+ * velocity i) and of M^-1, both row-major, reassembled from the symmetry blocks the
+ * kernels use; *cond (may be NULL) receives ||M||_inf ||M^-1||_inf.  Needs no device. */
+lbkm_status lbkm_get_matrices(lbkm_ctx* ctx, double* M, double* Minv, double* cond);
+
+/* Number of steps taken since init_fields / set_state. */
+lbkm_status lbkm_get_step_count(lbkm_ctx* ctx, int64_t* out);
+
+/* Discrete adjoint of one step (the transpose of the step's Jacobian).
+ * Given the level-n state (f_n [24][ny][nx], lam_n [ny][nx], dense device arrays)
+ * and the adjoint of the level-(n+1) state (af_np1, alam_np1, same layout), write
+ * the adjoint of the level-n state into af_n, alam_n and ADD this step's parameter
+ * gradient contributions to grad_params (device array of 27 doubles:
+ * d/dR_1..R_24, d/dQ, d/domega1, d/domega2).  R_8, R_9 are treated as independent
+ * parameters.  Asynchronous.  Branches (minmod selections, the ignition test)
+ * are frozen at the level-n values. */
+lbkm_status lbkm_adjoint_step(lbkm_ctx* ctx, const double* f_n, const double* lam_n,
+                              const double* af_np1, const double* alam_np1,
+                              double* af_n, double* alam_n, double* grad_params);
+
+/* Adjoint of lbkm_init_fields: given a_f = dL/df (dense [24][ny][nx]) and the
+ * initial macroscopic fields, write dL/d(rho, u_x, u_y, T) (dense [ny][nx]).
+ * Asynchronous. */
+lbkm_status lbkm_adjoint_init(lbkm_ctx* ctx, const double* rho, const double* ux,
+                              const double* uy, const double* T, const double* af,
+                              double* arho, double* aux, double* auy, double* aT);
+
+/* Loss L = sum_cells sum_{k=5..24} Delta_k^2 of a dense state f[24][ny][nx]
+ * (into *loss_dev, device) and its gradient dL/df into grad_f (dense, may be
+ * NULL).  Asynchronous. */
+lbkm_status lbkm_tne_loss(lbkm_ctx* ctx, const double* f, double* loss_dev, double* grad_f);
+
+/* Plain streaming copy of n doubles src -> dst (device pointers, 16-byte aligned) on
+ * hip_stream; a bandwidth reference for the step kernel's roofline (asynchronous). */
+lbkm_status lbkm_copy_kernel(const double* src, double* dst, int64_t n, void* hip_stream);
+
+const char* lbkm_last_error(const lbkm_ctx* ctx);
+lbkm_status lbkm_destroy(lbkm_ctx* ctx);
+
+/* ---- batched 1D instances ------------------------------------------------ */
+/* Many independent 1D runs (Ny = 1, outflow at both ends) of ragged lengths
+ * nx[k], sharing dx, dt, the velocity model, gamma, Q and the rate law, each with
+ * its own R_1..R_24.  The library owns the packed state (f[24][total] and
+ * lambda[total], instances laid out back to back).  One lbkm_batch_step call
+ * replays a captured HIP graph that advances every instance n steps with one
+ * persistent kernel launch per chunk of steps. */
+
+/* common->nx, ny, bc_x, bc_y are ignored (each instance is nx[k] x 1, outflow). */
+lbkm_status lbkm_batch_create(int32_t n_inst, const int32_t* nx, const lbkm_grid* common,
+                              void* hip_stream, lbkm_ctx** out);
+
+/* S: host [n_inst][24] rates; Pr: host [n_inst] or NULL (same meaning as in
+ * lbkm_set_params, per instance); gamma, Q and rates shared. */
+lbkm_status lbkm_batch_set_params(lbkm_ctx* ctx, const double* S, const double* Pr,
+                                  double gamma, double Q, const lbkm_rates* rates);
+
+/* Initial fields, packed back to back: rho, ux, uy, T, lambda of sum(nx) doubles
+ * each (device pointers). */
+lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
+                                   const double* uy, const double* T, const double* lambda);
+
+/* Choose the tile (cells per work-group) by timing candidates on this device
+ * (autotuner; the state is saved and restored around the trial runs).  If never
+ * called, a default tile is used.  *tile_out (host, may be NULL) receives the choice. */
+lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* tile_out);
+
+/* Advance every instance n steps (asynchronous; replays a captured graph). */
+lbkm_status lbkm_batch_step(lbkm_ctx* ctx, int64_t n);
+
+/* Packed macroscopic readout (sum(nx) doubles each, device, NULL allowed). */
+lbkm_status lbkm_batch_get_moments(lbkm_ctx* ctx, double* rho, double* ux, double* uy,
+                                   double* T, double* p, double* lambda);
+
+/* Total number of cells sum(nx) (host). */
+lbkm_status lbkm_batch_total_cells(lbkm_ctx* ctx, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBKM_H */

@@ -1,0 +1,342 @@
+// C ABI of liblbkm: context management, parameter validation and kernel launches.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbkm.h"
+#include "lbkm_abi_internal.h"
+#include "lbkm_kernels.h"
+
+using namespace lbkm;
+
+namespace lbkm {
+
+lbkm_status fail(lbkm_ctx* ctx, lbkm_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+lbkm_status hip_fail(lbkm_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, LBKM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite_all(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// I = 2/(gamma-1) - D, snapped to an integer within 1e-9 (gamma = (D+I+2)/(D+I), Sec. III)
+double internal_dof(double gamma) {
+    double I = 2.0 / (gamma - 1.0) - 2.0;
+    const double r = std::nearbyint(I);
+    if (std::fabs(I - r) <= 1e-9) I = r;
+    return I;
+}
+
+// Validate one rate set and write the physics part of the constants.  Shared by the
+// single-grid and the batched contexts.
+lbkm_status fill_physics(lbkm_ctx* ctx, Consts* c, const double S[24], double gamma, double Pr,
+                         double Q, const lbkm_rates* rates, double dt) {
+    if (!S || !rates) return fail(ctx, LBKM_EINVAL, "S and rates must not be NULL");
+    if (!std::isfinite(gamma) || !(gamma > 1.0))
+        return fail(ctx, LBKM_EINVAL, "gamma must be finite and > 1");
+    const double I = internal_dof(gamma);
+    if (!(I > 0.0)) return fail(ctx, LBKM_EINVAL, "gamma >= 2 gives I <= 0; C_i divides by I");
+    double R[24];
+    std::memcpy(R, S, sizeof(R));
+    if (!finite_all(R, 24)) return fail(ctx, LBKM_EINVAL, "non-finite relaxation rate");
+    if (std::isfinite(Pr) && Pr > 0.0) {
+        if (!(R[4] == R[5] && R[5] == R[6]))
+            return fail(ctx, LBKM_EINVAL, "Pr > 0 requires R_5 = R_6 = R_7");
+        R[7] = R[8] = Pr * R[4];
+    } else if (!std::isfinite(Pr)) {
+        return fail(ctx, LBKM_EINVAL, "Pr must be finite (<= 0 means: use S as given)");
+    }
+    for (int k = 0; k < 24; ++k) {
+        if (!(R[k] > 0.0)) return fail(ctx, LBKM_EINVAL, "R_" + std::to_string(k + 1) + " must be > 0");
+        if (k >= 4 && !(R[k] * dt < 2.0))
+            return fail(ctx, LBKM_EINVAL, "R_" + std::to_string(k + 1) +
+                                              " dt >= 2: forward Euler relaxation is unstable");
+    }
+    const double vals[] = {Q, rates->omega1, rates->omega2, rates->m, rates->n, rates->T_ig};
+    if (!finite_all(vals, 6)) return fail(ctx, LBKM_EINVAL, "non-finite Q or rate constant");
+    if (rates->omega1 < 0 || rates->omega2 < 0 || rates->m < 0 || rates->n < 0)
+        return fail(ctx, LBKM_EINVAL, "omega1, omega2, m, n must be >= 0");
+    if (rates->T_ig < 0) return fail(ctx, LBKM_EINVAL, "T_ig must be >= 0");
+    std::memcpy(c->R, R, sizeof(R));
+    c->I = I;
+    c->DI = 2.0 + I;
+    c->Q = Q;
+    c->w1 = rates->omega1;
+    c->w2 = rates->omega2;
+    c->pm = rates->m;
+    c->pn = rates->n;
+    c->m_is_one = rates->m == 1.0;
+    c->n_is_one = rates->n == 1.0;
+    c->Tig = rates->T_ig;
+    c->a8c = (R[4] - R[7]) / R[4];
+    c->a9c = (R[6] - R[8]) / R[6];
+    c->amod = (c->a8c != 0.0 || c->a9c != 0.0) ? 1 : 0;
+    c->chem = (rates->omega1 > 0.0 || rates->omega2 > 0.0) ? 1 : 0;
+    return LBKM_OK;
+}
+
+lbkm_status validate_grid_common(lbkm_ctx* ctx, const lbkm_grid* g) {
+    const double v[] = {g->dx, g->dy, g->dt, g->dvm.va, g->dvm.vb, g->dvm.vc,
+                        g->dvm.eta_a, g->dvm.eta_b, g->dvm.eta_c};
+    if (!finite_all(v, 9)) return fail(ctx, LBKM_EINVAL, "non-finite grid or velocity parameter");
+    if (!(g->dx > 0 && g->dy > 0 && g->dt > 0)) return fail(ctx, LBKM_EINVAL, "dx, dy, dt must be > 0");
+    if (!(g->dvm.va > 0 && g->dvm.vb > 0 && g->dvm.vc > 0))
+        return fail(ctx, LBKM_EINVAL, "group speeds must be > 0");
+    if (g->dvm.eta_a < 0 || g->dvm.eta_b < 0 || g->dvm.eta_c < 0)
+        return fail(ctx, LBKM_EINVAL, "eta parameters must be >= 0");
+    return LBKM_OK;
+}
+
+lbkm_status build_tables(lbkm_ctx* ctx, const lbkm_grid* g) {
+    const double dvm[6] = {g->dvm.va, g->dvm.vb, g->dvm.vc, g->dvm.eta_a, g->dvm.eta_b, g->dvm.eta_c};
+    std::memset(&ctx->h, 0, sizeof(Consts));
+    if (build_moment_blocks(dvm, &ctx->h, &ctx->cond) != 0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "moment matrix singular or ill-conditioned (cond_inf = %.3g)", ctx->cond);
+        return fail(ctx, LBKM_ESINGULAR, buf);
+    }
+    Consts& c = ctx->h;
+    c.dt = g->dt;
+    c.inv_dx = 1.0 / g->dx;
+    c.inv_dy = 1.0 / g->dy;
+    c.half_inv_dx = 1.0 / (2.0 * g->dx);
+    c.half_inv_dy = 1.0 / (2.0 * g->dy);
+    c.nx = g->nx;
+    c.ny = g->ny;
+    c.bc_x = g->bc_x;
+    c.bc_y = g->bc_y;
+    return LBKM_OK;
+}
+
+lbkm_status ensure_device_tables(lbkm_ctx* ctx) {
+    if (ctx->d) return LBKM_OK;
+    hipError_t e = hipMalloc((void**)&ctx->d, sizeof(Consts));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->partials, sizeof(double) * 8 * kReduceBlocks);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->out8, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->flag, sizeof(int));
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocation of library tables");
+    return LBKM_OK;
+}
+
+lbkm_status upload_consts(lbkm_ctx* ctx) {
+    lbkm_status st = ensure_device_tables(ctx);
+    if (st != LBKM_OK) return st;
+    hipError_t e = hipMemcpyAsync(ctx->d, &ctx->h, sizeof(Consts), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of constants");
+    e = hipStreamSynchronize(ctx->stream);   // the host copy may change before the next launch
+    if (e != hipSuccess) return hip_fail(ctx, e, "upload of constants");
+    return LBKM_OK;
+}
+
+}  // namespace lbkm
+
+extern "C" {
+
+lbkm_status lbkm_create(const lbkm_grid* grid, void* hip_stream, lbkm_ctx** out) {
+    if (!grid || !out) return LBKM_EINVAL;
+    *out = nullptr;
+    lbkm_ctx* ctx = new (std::nothrow) lbkm_ctx();
+    if (!ctx) return LBKM_ENOMEM;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->grid = *grid;
+    lbkm_status st = LBKM_OK;
+    if (grid->nx < 1 || grid->ny < 1) st = fail(ctx, LBKM_EINVAL, "nx and ny must be >= 1");
+    if (st == LBKM_OK && ((grid->bc_x != LBKM_BC_PERIODIC && grid->bc_x != LBKM_BC_OUTFLOW) ||
+                          (grid->bc_y != LBKM_BC_PERIODIC && grid->bc_y != LBKM_BC_OUTFLOW)))
+        st = fail(ctx, LBKM_EINVAL, "unknown boundary condition");
+    if (st == LBKM_OK) st = validate_grid_common(ctx, grid);
+    if (st == LBKM_OK) st = build_tables(ctx, grid);
+    if (st != LBKM_OK) {
+        // keep the context so that lbkm_last_error can report; caller must destroy it
+        *out = ctx;
+        return st;
+    }
+    *out = ctx;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b, double* lam_a, double* lam_b,
+                              int64_t pitch) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "bind_buffers is not used by batched contexts");
+    if (!f_a || !f_b || !lam_a || !lam_b) return fail(ctx, LBKM_EINVAL, "NULL buffer");
+    if (f_a == f_b || lam_a == lam_b) return fail(ctx, LBKM_EINVAL, "the two buffers of a pair must differ");
+    if (pitch < ctx->grid.nx) return fail(ctx, LBKM_EINVAL, "pitch < nx");
+    ctx->f[0] = f_a;
+    ctx->f[1] = f_b;
+    ctx->lam[0] = lam_a;
+    ctx->lam[1] = lam_b;
+    ctx->cur = 0;
+    ctx->pitch = pitch;
+    ctx->h.pitch = pitch;
+    ctx->h.plane = pitch * (int64_t)ctx->grid.ny;
+    ctx->fields = false;
+    lbkm_status st = ensure_device_tables(ctx);
+    if (st != LBKM_OK) return st;
+    ctx->bound = true;
+    return ctx->params ? upload_consts(ctx) : LBKM_OK;
+}
+
+lbkm_status lbkm_set_params(lbkm_ctx* ctx, const double S[24], double gamma, double Pr, double Q,
+                            const lbkm_rates* rates) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "use lbkm_batch_set_params on a batched context");
+    Consts trial = ctx->h;
+    lbkm_status st = fill_physics(ctx, &trial, S, gamma, Pr, Q, rates, ctx->grid.dt);
+    if (st != LBKM_OK) return st;
+    ctx->h = trial;
+    ctx->params = true;
+    return ctx->bound ? upload_consts(ctx) : LBKM_OK;
+}
+
+static lbkm_status ready(lbkm_ctx* ctx, bool need_fields) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
+    if (!ctx->bound) return fail(ctx, LBKM_ESTATE, "buffers not bound");
+    if (!ctx->params) return fail(ctx, LBKM_ESTATE, "parameters not set");
+    if (need_fields && !ctx->fields) return fail(ctx, LBKM_ESTATE, "fields not initialised");
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                             const double* T, const double* lambda) {
+    lbkm_status st = ready(ctx, false);
+    if (st != LBKM_OK) return st;
+    if (!rho || !ux || !uy || !T || !lambda) return fail(ctx, LBKM_EINVAL, "NULL field");
+    ctx->cur = 0;
+    hipError_t e = launch_init(ctx->d, ctx->grid.nx, ctx->grid.ny, rho, ux, uy, T, lambda, ctx->f[0],
+                               ctx->lam[0], ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "init kernel");
+    ctx->fields = true;
+    ctx->steps = 0;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    if (n < 0) return fail(ctx, LBKM_EINVAL, "n must be >= 0");
+    for (int64_t k = 0; k < n; ++k) {
+        const int a = ctx->cur, b = 1 - a;
+        hipError_t e = launch_step(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[a], ctx->f[b], ctx->lam[a],
+                                   ctx->lam[b], ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
+        ctx->cur = b;
+        ++ctx->steps;
+    }
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_get_moments(lbkm_ctx* ctx, double* rho, double* ux, double* uy, double* T, double* p,
+                             double* lambda) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    hipError_t e = launch_moments(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[ctx->cur], ctx->lam[ctx->cur],
+                                  rho, ux, uy, T, p, lambda, ctx->stream);
+    return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "moments kernel");
+}
+
+lbkm_status lbkm_get_tne(lbkm_ctx* ctx, double* delta, double* d) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    hipError_t e = launch_tne(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[ctx->cur], delta, d, ctx->stream);
+    return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "tne kernel");
+}
+
+lbkm_status lbkm_reduce(lbkm_ctx* ctx, double out[8]) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    if (!out) return fail(ctx, LBKM_EINVAL, "NULL output");
+    const int64_t cells = (int64_t)ctx->grid.nx * ctx->grid.ny;
+    int nb = (int)((cells + 255) / 256);
+    if (nb > kReduceBlocks) nb = kReduceBlocks;
+    hipError_t e = launch_reduce(ctx->d, ctx->f[ctx->cur], ctx->lam[ctx->cur], ctx->partials, nb, ctx->out8,
+                                 ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, ctx->out8, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduction");
+    out[5] *= ctx->grid.dx / ctx->grid.ny;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_check(lbkm_ctx* ctx) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    int flag = 0;
+    hipError_t e = launch_check(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[ctx->cur], ctx->lam[ctx->cur],
+                                ctx->flag, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "check");
+    if (flag) return fail(ctx, LBKM_ENONFINITE, "non-finite value, rho <= 0 or T <= 0 in the state");
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_get_state(lbkm_ctx* ctx, double* f, double* lam) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    hipError_t e = hipSuccess;
+    if (f) e = launch_copy_state(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[ctx->cur], f, 24, 1, ctx->stream);
+    if (e == hipSuccess && lam)
+        e = launch_copy_state(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->lam[ctx->cur], lam, 1, 1, ctx->stream);
+    return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "get_state");
+}
+
+lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam) {
+    lbkm_status st = ready(ctx, false);
+    if (st != LBKM_OK) return st;
+    if (!f || !lam) return fail(ctx, LBKM_EINVAL, "NULL state");
+    ctx->cur = 0;
+    hipError_t e = launch_copy_state(ctx->d, ctx->grid.nx, ctx->grid.ny, f, ctx->f[0], 24, 0, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_copy_state(ctx->d, ctx->grid.nx, ctx->grid.ny, lam, ctx->lam[0], 1, 0, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_state");
+    ctx->fields = true;
+    ctx->steps = 0;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_get_matrices(lbkm_ctx* ctx, double* M, double* Minv, double* cond) {
+    if (!ctx || !M || !Minv) return LBKM_EINVAL;
+    dense_from_blocks(&ctx->h, M, Minv);
+    if (cond) *cond = ctx->cond;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_get_step_count(lbkm_ctx* ctx, int64_t* out) {
+    if (!ctx || !out) return LBKM_EINVAL;
+    *out = ctx->steps;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_copy_kernel(const double* src, double* dst, int64_t n, void* hip_stream) {
+    if (!src || !dst || n < 0) return LBKM_EINVAL;
+    return launch_copy(src, dst, n, (hipStream_t)hip_stream) == hipSuccess ? LBKM_OK : LBKM_EDEVICE;
+}
+
+const char* lbkm_last_error(const lbkm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
+    if (!ctx) return LBKM_EINVAL;
+    destroy_extras(ctx);
+    if (ctx->d) (void)hipFree(ctx->d);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->out8) (void)hipFree(ctx->out8);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    delete ctx;
+    return LBKM_OK;
+}
+
+}  // extern "C"

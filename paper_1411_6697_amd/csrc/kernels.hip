@@ -1,0 +1,368 @@
+// HIP kernels of the single-grid MRT-LBKM path (gfx950, float64) and their launchers.
+//
+// State layout (structure of arrays): f[24][ny][pitch], lambda[ny][pitch].  One thread
+// updates one cell; a work-group covers a 64 x 4 tile so that each wavefront reads 64
+// consecutive cells of a row (512 contiguous bytes per velocity plane).
+
+#include <hip/hip_runtime.h>
+
+#include "lbkm_device.h"
+#include "lbkm_kernels.h"
+
+namespace lbkm {
+
+namespace {
+
+constexpr int TX = 64, TY = 4;
+
+struct Idx {
+    int64_t c, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2;   // element offsets in one plane
+};
+
+__device__ __forceinline__ Idx stencil_index(const Consts* __restrict__ c, int x, int y) {
+    const int nx = c->nx, ny = c->ny;
+    const int64_t p = c->pitch;
+    const int64_t row = (int64_t)y * p;
+    Idx s;
+    s.c = row + x;
+    s.xm2 = row + wrap(x - 2, nx, c->bc_x);
+    s.xm1 = row + wrap(x - 1, nx, c->bc_x);
+    s.xp1 = row + wrap(x + 1, nx, c->bc_x);
+    s.xp2 = row + wrap(x + 2, nx, c->bc_x);
+    s.ym2 = (int64_t)wrap(y - 2, ny, c->bc_y) * p + x;
+    s.ym1 = (int64_t)wrap(y - 1, ny, c->bc_y) * p + x;
+    s.yp1 = (int64_t)wrap(y + 1, ny, c->bc_y) * p + x;
+    s.yp2 = (int64_t)wrap(y + 2, ny, c->bc_y) * p + x;
+    return s;
+}
+
+__device__ __forceinline__ void load_cell(const double* __restrict__ f, int64_t plane, int64_t at,
+                                          double v[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = f[i * plane + at];
+}
+
+// one full time step for every cell (Sec. II; all inputs at level n)
+__global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c,
+                                                  const double* __restrict__ fin,
+                                                  double* __restrict__ fout,
+                                                  const double* __restrict__ lin,
+                                                  double* __restrict__ lout) {
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const int y = blockIdx.y * TY + threadIdx.y;
+    if (x >= c->nx || y >= c->ny) return;
+    const int64_t plane = c->plane;
+    const Idx s = stencil_index(c, x, y);
+
+    double f[NV];
+    load_cell(fin, plane, s.c, f);
+    Blocks sb, h;
+    to_combos(f, sb);
+    forward(c, sb, h);
+    const Macro m = macro_of(h, c->DI);
+
+    double A8 = 0.0, A9 = 0.0;
+    if (c->amod) {
+        double nb[NV], uxe, uye, uxw, uyw, uxn, uyn, uxs, uys;
+        load_cell(fin, plane, s.xp1, nb);
+        velocity_of(c, nb, uxe, uye);
+        load_cell(fin, plane, s.xm1, nb);
+        velocity_of(c, nb, uxw, uyw);
+        load_cell(fin, plane, s.yp1, nb);
+        velocity_of(c, nb, uxn, uyn);
+        load_cell(fin, plane, s.ym1, nb);
+        velocity_of(c, nb, uxs, uys);
+        modification(c, m, (uxe - uxw) * c->half_inv_dx, (uxn - uxs) * c->half_inv_dy,
+                     (uye - uyw) * c->half_inv_dx, (uyn - uys) * c->half_inv_dy, A8, A9);
+    }
+
+    const double lam = lin[s.c];
+    double src[NV], dlam;
+    local_source(c, f, lam, A8, A9, m, h, src, dlam);
+
+    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double v = c->vg[g];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int i = 8 * g + d;
+            const double* b = fin + i * plane;
+            double adv = 0.0;
+            if (DUX[d] > 0) adv += v * (nnd_pos(b[s.xm2], b[s.xm1], f[i], b[s.xp1]) * idx_);
+            if (DUX[d] < 0) adv -= v * (nnd_neg(b[s.xm1], f[i], b[s.xp1], b[s.xp2]) * idx_);
+            if (DUY[d] > 0) adv += v * (nnd_pos(b[s.ym2], b[s.ym1], f[i], b[s.yp1]) * idy);
+            if (DUY[d] < 0) adv -= v * (nnd_neg(b[s.ym1], f[i], b[s.yp1], b[s.yp2]) * idy);
+            fout[i * plane + s.c] = f[i] + dt * (src[i] - adv);
+        }
+    }
+    const double dlx = (m.ux > 0.0) ? nnd_pos(lin[s.xm2], lin[s.xm1], lam, lin[s.xp1])
+                                    : nnd_neg(lin[s.xm1], lam, lin[s.xp1], lin[s.xp2]);
+    const double dly = (m.uy > 0.0) ? nnd_pos(lin[s.ym2], lin[s.ym1], lam, lin[s.yp1])
+                                    : nnd_neg(lin[s.ym1], lam, lin[s.yp1], lin[s.yp2]);
+    lout[s.c] = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+}
+
+// f = M^-1 f_hat^eq(rho, u, T) (Eq. moment12), lambda copied; inputs dense [ny][nx]
+__global__ __launch_bounds__(256) void k_init(const Consts* __restrict__ c, const double* __restrict__ rho,
+                                              const double* __restrict__ ux, const double* __restrict__ uy,
+                                              const double* __restrict__ T, const double* __restrict__ lam,
+                                              double* __restrict__ f, double* __restrict__ lout) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t dn = (int64_t)y * c->nx + x, at = (int64_t)y * c->pitch + x;
+    Blocks e, s;
+    equilibrium(rho[dn], ux[dn], uy[dn], T[dn], c->I, e);
+    inverse(c, e, s);
+    double v[NV];
+    from_combos(s, v);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) f[i * c->plane + at] = v[i];
+    lout[at] = lam[dn];
+}
+
+__device__ __forceinline__ void natural_delta(const Blocks& h, const Blocks& e, double dk[NV]) {
+#pragma unroll
+    for (int r = 0; r < NEE; ++r) dk[EE_M[r]] = h.ee[r] - e.ee[r];
+#pragma unroll
+    for (int r = 0; r < NOE; ++r) dk[OE_M[r]] = h.oe[r] - e.oe[r];
+#pragma unroll
+    for (int r = 0; r < NEO; ++r) dk[EO_M[r]] = h.eo[r] - e.eo[r];
+#pragma unroll
+    for (int r = 0; r < NOO; ++r) dk[OO_M[r]] = h.oo[r] - e.oo[r];
+}
+
+__global__ __launch_bounds__(256) void k_moments(const Consts* __restrict__ c, const double* __restrict__ f,
+                                                 const double* __restrict__ lam, double* rho, double* ux,
+                                                 double* uy, double* T, double* p, double* lout) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t dn = (int64_t)y * c->nx + x, at = (int64_t)y * c->pitch + x;
+    double v[NV];
+    load_cell(f, c->plane, at, v);
+    Blocks s, h;
+    to_combos(v, s);
+    forward(c, s, h);
+    const Macro m = macro_of(h, c->DI);
+    if (rho) rho[dn] = m.rho;
+    if (ux) ux[dn] = m.ux;
+    if (uy) uy[dn] = m.uy;
+    if (T) T[dn] = m.T;
+    if (p) p[dn] = m.rho * m.T;
+    if (lout) lout[dn] = lam[at];
+}
+
+__global__ __launch_bounds__(256) void k_tne(const Consts* __restrict__ c, const double* __restrict__ f,
+                                             double* delta, double* dist) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t dn = (int64_t)y * c->nx + x, at = (int64_t)y * c->pitch + x;
+    const int64_t cells = (int64_t)c->nx * c->ny;
+    double v[NV];
+    load_cell(f, c->plane, at, v);
+    Blocks s, h, e;
+    to_combos(v, s);
+    forward(c, s, h);
+    const Macro m = macro_of(h, c->DI);
+    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+    double dk[NV];
+    natural_delta(h, e, dk);
+    double ss = 0.0;
+#pragma unroll
+    for (int k = 4; k < NV; ++k) {
+        if (delta) delta[(k - 4) * cells + dn] = dk[k];
+        ss = fma(dk[k], dk[k], ss);
+    }
+    if (dist) dist[dn] = sqrt(ss);
+}
+
+// wave64 + work-group reduction of 8 values (sum x6, min, max); deterministic order
+__device__ __forceinline__ void block_reduce8(double v[8], double* sh /*[4][8]*/) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] += __shfl_xor(v[k], off, 64);
+        v[6] = fmin(v[6], __shfl_xor(v[6], off, 64));
+        v[7] = fmax(v[7], __shfl_xor(v[7], off, 64));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 8; ++k) sh[wave * 8 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            for (int k = 0; k < 6; ++k) v[k] += sh[w * 8 + k];
+            v[6] = fmin(v[6], sh[w * 8 + 6]);
+            v[7] = fmax(v[7], sh[w * 8 + 7]);
+        }
+    }
+}
+
+// per-work-group partial reductions over a grid-stride range of cells
+__global__ __launch_bounds__(256) void k_reduce_partial(const Consts* __restrict__ c,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ lam,
+                                                        double* __restrict__ partials) {
+    __shared__ double sh[4 * 8];
+    const int64_t cells = (int64_t)c->nx * c->ny;
+    double v[8] = {0, 0, 0, 0, 0, 0, INFINITY, -INFINITY};
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cells;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(q / c->nx), x = (int)(q % c->nx);
+        const int64_t at = (int64_t)y * c->pitch + x;
+        double fv[NV];
+        load_cell(f, c->plane, at, fv);
+        Blocks s, h, e;
+        to_combos(fv, s);
+        forward(c, s, h);
+        const Macro m = macro_of(h, c->DI);
+        equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+        double dk[NV];
+        natural_delta(h, e, dk);
+        double ss = 0.0;
+#pragma unroll
+        for (int k = 4; k < NV; ++k) ss = fma(dk[k], dk[k], ss);
+        v[0] += h.ee[0];
+        v[1] += h.oe[0];
+        v[2] += h.eo[0];
+        v[3] += 0.5 * h.ee[1];
+        v[4] += ss;
+        v[5] += fabs(dk[4]);
+        const double l = lam[at];
+        v[6] = fmin(v[6], l);
+        v[7] = fmax(v[7], l);
+    }
+    block_reduce8(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) partials[blockIdx.x * 8 + k] = v[k];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int n,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[4 * 8];
+    double v[8] = {0, 0, 0, 0, 0, 0, INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < n; b += blockDim.x) {
+        for (int k = 0; k < 6; ++k) v[k] += partials[b * 8 + k];
+        v[6] = fmin(v[6], partials[b * 8 + 6]);
+        v[7] = fmax(v[7], partials[b * 8 + 7]);
+    }
+    block_reduce8(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) out[k] = v[k];
+}
+
+// health check: NaN/Inf anywhere in f or lambda, rho <= 0 or T <= 0
+__global__ __launch_bounds__(256) void k_check(const Consts* __restrict__ c, const double* __restrict__ f,
+                                               const double* __restrict__ lam, int* flag) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t at = (int64_t)y * c->pitch + x;
+    double v[NV];
+    load_cell(f, c->plane, at, v);
+    bool bad = !isfinite(lam[at]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) bad |= !isfinite(v[i]);
+    Blocks s, h;
+    to_combos(v, s);
+    forward(c, s, h);
+    const Macro m = macro_of(h, c->DI);
+    bad |= !(m.rho > 0.0) || !(m.T > 0.0);
+    if (bad) atomicOr(flag, 1);
+}
+
+// pitched <-> dense copies of the state
+__global__ __launch_bounds__(256) void k_copy_state(const Consts* __restrict__ c, const double* __restrict__ src,
+                                                    double* __restrict__ dst, int planes, int to_dense) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t cells = (int64_t)c->nx * c->ny;
+    const int64_t dn = (int64_t)y * c->nx + x, at = (int64_t)y * c->pitch + x;
+    for (int i = 0; i < planes; ++i) {
+        if (to_dense)
+            dst[i * cells + dn] = src[i * c->plane + at];
+        else
+            dst[i * c->plane + at] = src[i * cells + dn];
+    }
+}
+
+__global__ void k_fill_int(int* p, int v) { *p = v; }
+
+// plain streaming copy (bandwidth calibration): 16-byte accesses, four per thread
+__global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                              int64_t n2) {
+    const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n2) dst[i] = src[i];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_step(const Consts* dc, int nx, int ny, const double* fin, double* fout,
+                       const double* lin, double* lout, hipStream_t st) {
+    dim3 grid((nx + TX - 1) / TX, (ny + TY - 1) / TY), block(TX, TY);
+    hipLaunchKernelGGL(k_step, grid, block, 0, st, dc, fin, fout, lin, lout);
+    return hipGetLastError();
+}
+
+static dim3 row_grid(int nx, int ny) { return dim3((nx + 255) / 256, ny); }
+
+hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,
+                       const double* uy, const double* T, const double* lam, double* f, double* lout,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_init, row_grid(nx, ny), dim3(256), 0, st, dc, rho, ux, uy, T, lam, f, lout);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const Consts* dc, int nx, int ny, const double* f, const double* lam,
+                          double* rho, double* ux, double* uy, double* T, double* p, double* lout,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_moments, row_grid(nx, ny), dim3(256), 0, st, dc, f, lam, rho, ux, uy, T, p, lout);
+    return hipGetLastError();
+}
+
+hipError_t launch_tne(const Consts* dc, int nx, int ny, const double* f, double* delta, double* dist,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_tne, row_grid(nx, ny), dim3(256), 0, st, dc, f, delta, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Consts* dc, const double* f, const double* lam, double* partials,
+                         int nblocks, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(256), 0, st, dc, f, lam, partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const Consts* dc, int nx, int ny, const double* f, const double* lam, int* flag,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, st, flag, 0);
+    hipLaunchKernelGGL(k_check, row_grid(nx, ny), dim3(256), 0, st, dc, f, lam, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(const Consts* dc, int nx, int ny, const double* src, double* dst, int planes,
+                             int to_dense, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_state, row_grid(nx, ny), dim3(256), 0, st, dc, src, dst, planes, to_dense);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
+    const int64_t n2 = n / 2;
+    if (n2 > 0)
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 1023) / 1024)), dim3(256), 0, st, (const double2*)src,
+                           (double2*)dst, n2);
+    if (n & 1) (void)hipMemcpyAsync(dst + n - 1, src + n - 1, sizeof(double), hipMemcpyDeviceToDevice, st);
+    return hipGetLastError();
+}
+
+}  // namespace lbkm

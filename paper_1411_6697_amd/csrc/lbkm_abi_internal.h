@@ -1,0 +1,47 @@
+// Context structure behind the opaque lbkm_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbkm.h"
+#include "lbkm_internal.h"
+
+namespace lbkm {
+constexpr int kReduceBlocks = 1024;   // per-work-group partials of lbkm_reduce
+struct BatchState;                    // batched contexts (batch.hip)
+}
+
+struct lbkm_ctx {
+    lbkm_grid grid{};
+    hipStream_t stream = nullptr;
+    int batched = 0;
+    double* f[2] = {nullptr, nullptr};
+    double* lam[2] = {nullptr, nullptr};
+    int64_t pitch = 0;
+    int cur = 0;
+    bool bound = false, params = false, fields = false;
+    int64_t steps = 0;
+    double cond = 0.0;
+    lbkm::Consts h{};                  // host copy of the device constants
+    lbkm::Consts* d = nullptr;         // device constants
+    double* partials = nullptr;        // reduction scratch
+    double* out8 = nullptr;
+    int* flag = nullptr;
+    lbkm::BatchState* batch = nullptr;
+    std::string err;
+};
+
+namespace lbkm {
+lbkm_status fail(lbkm_ctx* ctx, lbkm_status st, const std::string& msg);
+lbkm_status hip_fail(lbkm_ctx* ctx, hipError_t e, const char* what);
+lbkm_status fill_physics(lbkm_ctx* ctx, Consts* c, const double S[24], double gamma, double Pr, double Q,
+                         const lbkm_rates* rates, double dt);
+lbkm_status validate_grid_common(lbkm_ctx* ctx, const lbkm_grid* g);
+lbkm_status build_tables(lbkm_ctx* ctx, const lbkm_grid* g);
+lbkm_status upload_consts(lbkm_ctx* ctx);
+lbkm_status ensure_device_tables(lbkm_ctx* ctx);
+void destroy_extras(lbkm_ctx* ctx);
+}  // namespace lbkm

@@ -1,0 +1,273 @@
+// Device-side building blocks of the MRT-LBKM step (gfx950, float64).
+//
+// The per-cell arithmetic is expressed in the mirror-symmetry basis of the velocity set
+// (see lbkm_internal.h): f_hat = M f costs 36 additions plus 162 multiply-adds instead of
+// 576, and M^-1 g the same.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbkm_internal.h"
+
+namespace lbkm {
+
+// direction table inside a group
+__device__ constexpr int DUX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int DUY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+
+struct Blocks {
+    double ee[NEE], oe[NOE], eo[NEO], oo[NOO];
+};
+
+// Symmetric combinations s = P f of the 24 values of one cell.
+__device__ __forceinline__ void to_combos(const double f[NV], Blocks& s) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double a0 = f[8 * g + 0], a1 = f[8 * g + 1], a2 = f[8 * g + 2], a3 = f[8 * g + 3];
+        const double d0 = f[8 * g + 4], d1 = f[8 * g + 5], d2 = f[8 * g + 6], d3 = f[8 * g + 7];
+        const double t1 = d0 + d2, t2 = d1 + d3, t3 = d0 - d2, t4 = d1 - d3;
+        s.ee[3 * g + 0] = a0 + a2;
+        s.ee[3 * g + 1] = a1 + a3;
+        s.ee[3 * g + 2] = t1 + t2;
+        s.oe[2 * g + 0] = a0 - a2;
+        s.oe[2 * g + 1] = t3 - t4;
+        s.eo[2 * g + 0] = a1 - a3;
+        s.eo[2 * g + 1] = t3 + t4;
+        s.oo[g] = t1 - t2;
+    }
+}
+
+// f from combination-space values (the 1/2, 1/4 factors are already in the C blocks).
+__device__ __forceinline__ void from_combos(const Blocks& s, double f[NV]) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double e1 = s.ee[3 * g + 0], e2 = s.ee[3 * g + 1], e3 = s.ee[3 * g + 2];
+        const double o1 = s.oe[2 * g + 0], o2 = s.oe[2 * g + 1];
+        const double q1 = s.eo[2 * g + 0], q2 = s.eo[2 * g + 1];
+        const double r1 = s.oo[g];
+        f[8 * g + 0] = e1 + o1;
+        f[8 * g + 2] = e1 - o1;
+        f[8 * g + 1] = e2 + q1;
+        f[8 * g + 3] = e2 - q1;
+        const double u1 = e3 + r1, u2 = e3 - r1, w1 = o2 + q2, w2 = q2 - o2;
+        f[8 * g + 4] = u1 + w1;
+        f[8 * g + 5] = u2 + w2;
+        f[8 * g + 6] = u1 - w1;
+        f[8 * g + 7] = u2 - w2;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void matvec(const double (*A)[N], const double* x, double* y) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc = fma(A[r][k], x[k], acc);
+        y[r] = acc;
+    }
+}
+
+// f_hat = M f in block order
+__device__ __forceinline__ void forward(const Consts* __restrict__ c, const Blocks& s, Blocks& h) {
+    matvec<NEE>(c->BEE, s.ee, h.ee);
+    matvec<NOE>(c->BOE, s.oe, h.oe);
+    matvec<NEO>(c->BEO, s.eo, h.eo);
+    matvec<NOO>(c->BOO, s.oo, h.oo);
+}
+
+// combination values of M^-1 g
+__device__ __forceinline__ void inverse(const Consts* __restrict__ c, const Blocks& g, Blocks& s) {
+    matvec<NEE>(c->CEE, g.ee, s.ee);
+    matvec<NOE>(c->COE, g.oe, s.oe);
+    matvec<NEO>(c->CEO, g.eo, s.eo);
+    matvec<NOO>(c->COO, g.oo, s.oo);
+}
+
+// Equilibrium moments f_hat^eq (Sec. II closed forms, factor T in entries 14 and 16 as
+// Eq. moment7 requires), D = 2, in block order.
+__device__ __forceinline__ void equilibrium(double rho, double ux, double uy, double T, double I,
+                                            Blocks& e) {
+    const double D = 2.0;
+    const double u2 = ux * ux + uy * uy;
+    const double a2 = (D + I + 2.0) * T + u2;
+    const double a4 = (D + I + 4.0) * T + u2;
+    const double c10 = u2 * u2 + (D + 2.0) * (D + I + 4.0) * T * T + (2.0 * D + I + 8.0) * u2 * T;
+    const double c11 = u2 + (D + 3.0 * I + 2.0) * T;
+    const double rT = rho * T, rIT = rho * I * T;
+    // EE: m1 m4 m5 m7 m14 m16 m17 m19 m20
+    e.ee[0] = rho;
+    e.ee[1] = rho * ((D + I) * T + u2);
+    e.ee[2] = rho * (T + ux * ux);
+    e.ee[3] = rho * (T + uy * uy);
+    e.ee[4] = rho * a2 * T + rho * ux * ux * a4;
+    e.ee[5] = rho * a2 * T + rho * uy * uy * a4;
+    e.ee[6] = rIT * T + rIT * ux * ux;
+    e.ee[7] = rIT * T + rIT * uy * uy;
+    e.ee[8] = rIT * (u2 + (D + 3.0 * I) * T);
+    // OE: m2 m8 m10 m12 m21 m23
+    e.oe[0] = rho * ux;
+    e.oe[1] = rho * ux * a2;
+    e.oe[2] = 3.0 * rT * ux + rho * ux * ux * ux;
+    e.oe[3] = rT * ux + rho * ux * uy * uy;
+    e.oe[4] = rho * ux * c10;
+    e.oe[5] = rIT * ux * c11;
+    // EO: m3 m9 m11 m13 m22 m24
+    e.eo[0] = rho * uy;
+    e.eo[1] = rho * uy * a2;
+    e.eo[2] = rT * uy + rho * ux * ux * uy;
+    e.eo[3] = 3.0 * rT * uy + rho * uy * uy * uy;
+    e.eo[4] = rho * uy * c10;
+    e.eo[5] = rIT * uy * c11;
+    // OO: m6 m15 m18
+    e.oo[0] = rho * ux * uy;
+    e.oo[1] = rho * ux * uy * a4;
+    e.oo[2] = rIT * ux * uy;
+}
+
+// R_k of each block slot (0-based moment indices, see lbkm_internal.h)
+__device__ constexpr int EE_M[NEE] = {0, 3, 4, 6, 13, 15, 16, 18, 19};
+__device__ constexpr int OE_M[NOE] = {1, 7, 9, 11, 20, 22};
+__device__ constexpr int EO_M[NEO] = {2, 8, 10, 12, 21, 23};
+__device__ constexpr int OO_M[NOO] = {5, 14, 17};
+
+// macroscopic variables from the conserved moments (Eqs. moment1-moment3)
+struct Macro {
+    double rho, ux, uy, T;
+};
+
+__device__ __forceinline__ Macro macro_of(const Blocks& h, double DI) {
+    Macro m;
+    m.rho = h.ee[0];
+    m.ux = h.oe[0] / m.rho;
+    m.uy = h.eo[0] / m.rho;
+    m.T = (h.ee[1] / m.rho - m.ux * m.ux - m.uy * m.uy) / DI;
+    return m;
+}
+
+// rho, j_x, j_y of a cell straight from its 24 values (used for neighbour velocities)
+__device__ __forceinline__ void velocity_of(const Consts* __restrict__ c, const double f[NV],
+                                            double& ux, double& uy) {
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double* q = f + 8 * g;
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) s += q[d];
+        rho += s;
+        jx = fma(c->vg[g], (q[0] - q[2]) + (q[4] - q[5]) + (q[7] - q[6]), jx);
+        jy = fma(c->vg[g], (q[1] - q[3]) + (q[4] + q[5]) - (q[6] + q[7]), jy);
+    }
+    ux = jx / rho;
+    uy = jy / rho;
+}
+
+// minmod: the argument of smaller magnitude if both have the same strict sign, else 0
+__device__ __forceinline__ double minmod(double a, double b) {
+    return (a > 0.0 && b > 0.0) ? fmin(a, b) : ((a < 0.0 && b < 0.0) ? fmax(a, b) : 0.0);
+}
+
+// NND differences h_{j+1/2} - h_{j-1/2} (to be divided by the spacing), Zhang 1988,
+// flux-split minmod form.  Positive speed uses j-2..j+1, negative speed j-1..j+2.
+__device__ __forceinline__ double nnd_pos(double fm2, double fm1, double f0, double fp1) {
+    const double hp = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);
+    const double hm = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);
+    return hp - hm;
+}
+__device__ __forceinline__ double nnd_neg(double fm1, double f0, double fp1, double fp2) {
+    const double hp = fp1 - 0.5 * minmod(fp1 - f0, fp2 - fp1);
+    const double hm = f0 - 0.5 * minmod(f0 - fm1, fp1 - f0);
+    return hp - hm;
+}
+
+// Cochran increment of lambda over one step, p frozen (exact solution of the Bernoulli
+// equation d(1-lambda)/dt = -(1-lambda)(a + b lambda)); zero unless T > T_ig,
+// lambda < 1 and a + b > 0.
+__device__ __forceinline__ double cochran(const Consts* __restrict__ c, double lam, double p, double T) {
+    if (!c->chem) return 0.0;
+    const double a = c->w1 * (c->m_is_one ? p : pow(p, c->pm));
+    const double b = c->w2 * (c->n_is_one ? p : pow(p, c->pn));
+    const double cc = a + b;
+    if (!(T > c->Tig && lam < 1.0 && cc > 0.0)) return 0.0;
+    const double y0 = 1.0 - lam;
+    const double E = exp(cc * c->dt);
+    const double y1 = cc * y0 / (b * y0 + (cc - b * y0) * E);
+    return y0 - y1;
+}
+
+// Collision and chemistry of one cell.
+// Input: f (24 values of the cell), lam, A8/A9 (modification terms, 0 if inactive).
+// Output: src[i] = -Omega_i + C_i (the non-streaming right-hand side) and dlam.
+__device__ __forceinline__ void local_source(const Consts* __restrict__ c, const double f[NV],
+                                             double lam, double A8, double A9, const Macro& m,
+                                             const Blocks& h, double src[NV], double& dlam) {
+    Blocks e;
+    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+    // g = R (f_hat - f_hat^eq) - A_hat, Delta_1..4 = 0
+    Blocks g;
+#pragma unroll
+    for (int r = 0; r < NEE; ++r) g.ee[r] = c->R[EE_M[r]] * (h.ee[r] - e.ee[r]);
+#pragma unroll
+    for (int r = 0; r < NOE; ++r) g.oe[r] = c->R[OE_M[r]] * (h.oe[r] - e.oe[r]);
+#pragma unroll
+    for (int r = 0; r < NEO; ++r) g.eo[r] = c->R[EO_M[r]] * (h.eo[r] - e.eo[r]);
+#pragma unroll
+    for (int r = 0; r < NOO; ++r) g.oo[r] = c->R[OO_M[r]] * (h.oo[r] - e.oo[r]);
+    g.ee[0] = 0.0;   // m1
+    g.ee[1] = 0.0;   // m4
+    g.oe[0] = 0.0;   // m2
+    g.eo[0] = 0.0;   // m3
+    g.oe[1] -= A8;   // m8
+    g.eo[1] -= A9;   // m9
+    Blocks s;
+    inverse(c, g, s);
+    double om[NV];
+    from_combos(s, om);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) src[i] = -om[i];
+
+    dlam = cochran(c, lam, m.rho * m.T, m.T);
+    if (dlam != 0.0) {
+        // C_i = f^eq_i Q [-(1+D) I T + I |v_i - u|^2 + eta_i^2] F / (I (D+I) T^2), F = dlam/dt
+        Blocks se;
+        inverse(c, e, se);
+        double feq[NV];
+        from_combos(se, feq);
+        const double F = dlam / c->dt;
+        const double common = c->Q * F / (c->I * c->DI * m.T * m.T);
+        const double base = -(1.0 + 2.0) * c->I * m.T;
+#pragma unroll
+        for (int g2 = 0; g2 < 3; ++g2)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const double cx = c->vg[g2] * DUX[d] - m.ux;
+                const double cy = c->vg[g2] * DUY[d] - m.uy;
+                const double br = base + c->I * (cx * cx + cy * cy) + c->eta2[g2];
+                src[8 * g2 + d] += feq[8 * g2 + d] * (common * br);
+            }
+    }
+}
+
+// A_hat_8, A_hat_9 (Eqs. ArtificialA8/ArtificialA9) from central differences of u
+__device__ __forceinline__ void modification(const Consts* __restrict__ c, const Macro& m,
+                                             double dux_dx, double dux_dy, double duy_dx,
+                                             double duy_dy, double& A8, double& A9) {
+    const double rT = m.rho * m.T;
+    const double iDI = 1.0 / c->DI;
+    A8 = rT * c->a8c * (4.0 * m.ux * (dux_dx - dux_dx * iDI - duy_dy * iDI) +
+                        2.0 * m.uy * (duy_dx + dux_dy));
+    A9 = rT * c->a9c * (4.0 * m.uy * (duy_dy - dux_dx * iDI - duy_dy * iDI) +
+                        2.0 * m.ux * (duy_dx + dux_dy));
+}
+
+// neighbour index along one axis with the boundary rule (periodic wrap or clamp)
+__device__ __forceinline__ int wrap(int j, int n, int bc) {
+    if (bc == 0) {   // periodic
+        j %= n;
+        return j < 0 ? j + n : j;
+    }
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+}  // namespace lbkm

@@ -1,0 +1,29 @@
+// Launchers of the HIP kernels (defined in kernels.hip), called by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbkm_internal.h"
+
+namespace lbkm {
+
+hipError_t launch_step(const Consts* dc, int nx, int ny, const double* fin, double* fout,
+                       const double* lin, double* lout, hipStream_t st);
+hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,
+                       const double* uy, const double* T, const double* lam, double* f, double* lout,
+                       hipStream_t st);
+hipError_t launch_moments(const Consts* dc, int nx, int ny, const double* f, const double* lam,
+                          double* rho, double* ux, double* uy, double* T, double* p, double* lout,
+                          hipStream_t st);
+hipError_t launch_tne(const Consts* dc, int nx, int ny, const double* f, double* delta, double* dist,
+                      hipStream_t st);
+hipError_t launch_reduce(const Consts* dc, const double* f, const double* lam, double* partials,
+                         int nblocks, double* out, hipStream_t st);
+hipError_t launch_check(const Consts* dc, int nx, int ny, const double* f, const double* lam, int* flag,
+                        hipStream_t st);
+hipError_t launch_copy_state(const Consts* dc, int nx, int ny, const double* src, double* dst, int planes,
+                             int to_dense, hipStream_t st);
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
+}  // namespace lbkm

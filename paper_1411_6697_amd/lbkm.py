@@ -1,0 +1,238 @@
+"""Thin ctypes binding of liblbkm (C ABI in include/lbkm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of the
+library.  PyTorch supplies device memory (caller-owned state buffers) and the stream.
+The binding refuses to run if the library is missing; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbkm.so")
+
+LBKM_BC_PERIODIC = 0
+LBKM_BC_OUTFLOW = 1
+BC = {"periodic": LBKM_BC_PERIODIC, "outflow": LBKM_BC_OUTFLOW}
+
+STATUS = {0: "LBKM_OK", -1: "LBKM_EINVAL", -2: "LBKM_ESINGULAR", -3: "LBKM_ENOMEM",
+          -4: "LBKM_EDEVICE", -5: "LBKM_ESTATE", -6: "LBKM_ENONFINITE"}
+
+
+class LbkmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dvm(ctypes.Structure):
+    _fields_ = [("va", ctypes.c_double), ("vb", ctypes.c_double), ("vc", ctypes.c_double),
+                ("eta_a", ctypes.c_double), ("eta_b", ctypes.c_double), ("eta_c", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("dt", ctypes.c_double), ("bc_x", ctypes.c_int32),
+                ("bc_y", ctypes.c_int32), ("dvm", Dvm)]
+
+
+class Rates(ctypes.Structure):
+    _fields_ = [("omega1", ctypes.c_double), ("omega2", ctypes.c_double), ("m", ctypes.c_double),
+                ("n", ctypes.c_double), ("T_ig", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "lbkm_create": [ctypes.POINTER(Grid), _P, ctypes.POINTER(_P)],
+    "lbkm_bind_buffers": [_P, _P, _P, _P, _P, ctypes.c_int64],
+    "lbkm_set_params": [_P, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Rates)],
+    "lbkm_init_fields": [_P, _P, _P, _P, _P, _P],
+    "lbkm_step": [_P, ctypes.c_int64],
+    "lbkm_get_moments": [_P, _P, _P, _P, _P, _P, _P],
+    "lbkm_get_tne": [_P, _P, _P],
+    "lbkm_reduce": [_P, _D],
+    "lbkm_check": [_P],
+    "lbkm_get_state": [_P, _P, _P],
+    "lbkm_set_state": [_P, _P, _P],
+    "lbkm_get_step_count": [_P, ctypes.POINTER(ctypes.c_int64)],
+    "lbkm_get_matrices": [_P, _D, _D, _D],
+    "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "lbkm_tne_loss": [_P, _P, _P, _P],
+    "lbkm_destroy": [_P],
+    "lbkm_copy_kernel": [_P, _P, ctypes.c_int64, _P],
+    "lbkm_batch_create": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Grid), _P,
+                          ctypes.POINTER(_P)],
+    "lbkm_batch_set_params": [_P, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Rates)],
+    "lbkm_batch_init_fields": [_P, _P, _P, _P, _P, _P],
+    "lbkm_batch_autotune": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "lbkm_batch_step": [_P, ctypes.c_int64],
+    "lbkm_batch_get_moments": [_P, _P, _P, _P, _P, _P, _P],
+    "lbkm_batch_total_cells": [_P, ctypes.POINTER(ctypes.c_int64)],
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblbkm.so (built by paper_1411_6697_amd.build).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1411_6697_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lbkm_last_error.argtypes = [_P]
+    lib.lbkm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(a, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def pad_pitch(nx: int, align: int = 64) -> int:
+    return (nx + align - 1) // align * align
+
+
+class Sim:
+    """One grid.  State buffers are torch tensors owned by this object."""
+
+    def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, dvm: Sequence[float],
+                 bc_x: str = "outflow", bc_y: str = "periodic", device="cuda:0",
+                 pitch: Optional[int] = None):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.nx, self.ny = int(nx), int(ny)
+        g = Grid(nx=self.nx, ny=self.ny, dx=dx, dy=dy, dt=dt, bc_x=BC[bc_x], bc_y=BC[bc_y],
+                 dvm=Dvm(*[float(v) for v in dvm]))
+        self._grid = g
+        h = ctypes.c_void_p()
+        st = self.lib.lbkm_create(ctypes.byref(g), _stream_handle(self.device), ctypes.byref(h))
+        self.h = h
+        if st != 0:
+            msg = self.lib.lbkm_last_error(h).decode() if h.value else "lbkm_create failed"
+            if h.value:
+                self.lib.lbkm_destroy(h)
+                self.h = ctypes.c_void_p()
+            raise LbkmError(st, msg)
+        self.pitch = int(pitch) if pitch is not None else pad_pitch(self.nx)
+        kw = dict(dtype=torch.float64, device=self.device)
+        self.f = [torch.zeros(24, self.ny, self.pitch, **kw), torch.zeros(24, self.ny, self.pitch, **kw)]
+        self.lam = [torch.zeros(self.ny, self.pitch, **kw), torch.zeros(self.ny, self.pitch, **kw)]
+        self._call("lbkm_bind_buffers", _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.lam[0]),
+                   _ptr(self.lam[1]), ctypes.c_int64(self.pitch))
+
+    # -- plumbing
+    def _call(self, name, *args):
+        st = getattr(self.lib, name)(self.h, *args)
+        if st != 0:
+            raise LbkmError(st, self.lib.lbkm_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lbkm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API
+    def set_params(self, S: Sequence[float], gamma: float, Pr: float = 0.0, Q: float = 0.0,
+                   omega1: float = 0.0, omega2: float = 0.0, m: float = 1.0, n: float = 1.0,
+                   T_ig: float = 1.1):
+        arr = (ctypes.c_double * 24)(*[float(v) for v in S])
+        r = Rates(omega1=omega1, omega2=omega2, m=m, n=n, T_ig=T_ig)
+        self._call("lbkm_set_params", arr, ctypes.c_double(gamma), ctypes.c_double(Pr),
+                   ctypes.c_double(Q), ctypes.byref(r))
+
+    def init_fields(self, rho, ux, uy, T, lam):
+        t = [_dev(a, self.device).reshape(self.ny, self.nx).contiguous() for a in (rho, ux, uy, T, lam)]
+        self._call("lbkm_init_fields", *[_ptr(a) for a in t])
+        self._keep = t          # keep inputs alive until the stream has consumed them
+
+    def step(self, n: int = 1):
+        self._call("lbkm_step", ctypes.c_int64(int(n)))
+
+    def moments(self) -> Dict[str, torch.Tensor]:
+        out = {k: torch.empty(self.ny, self.nx, dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "T", "p", "lam")}
+        self._call("lbkm_get_moments", *[_ptr(out[k]) for k in ("rho", "ux", "uy", "T", "p", "lam")])
+        return out
+
+    def tne(self):
+        delta = torch.empty(20, self.ny, self.nx, dtype=torch.float64, device=self.device)
+        d = torch.empty(self.ny, self.nx, dtype=torch.float64, device=self.device)
+        self._call("lbkm_get_tne", _ptr(delta), _ptr(d))
+        return delta, d
+
+    def reduce(self) -> np.ndarray:
+        out = (ctypes.c_double * 8)()
+        self._call("lbkm_reduce", out)
+        return np.array(out[:], dtype=np.float64)
+
+    def check(self) -> bool:
+        st = self.lib.lbkm_check(self.h)
+        if st == -6:
+            return False
+        if st != 0:
+            raise LbkmError(st, self.lib.lbkm_last_error(self.h).decode())
+        return True
+
+    def get_state(self):
+        f = torch.empty(24, self.ny, self.nx, dtype=torch.float64, device=self.device)
+        lam = torch.empty(self.ny, self.nx, dtype=torch.float64, device=self.device)
+        self._call("lbkm_get_state", _ptr(f), _ptr(lam))
+        return f, lam
+
+    def set_state(self, f, lam):
+        f = _dev(f, self.device).reshape(24, self.ny, self.nx).contiguous()
+        lam = _dev(lam, self.device).reshape(self.ny, self.nx).contiguous()
+        self._call("lbkm_set_state", _ptr(f), _ptr(lam))
+        self._keep = (f, lam)
+
+    def step_count(self) -> int:
+        v = ctypes.c_int64()
+        self._call("lbkm_get_step_count", ctypes.byref(v))
+        return v.value
+
+
+def sim_from_workload(w, device="cuda:0", pitch=None, fields=None) -> Sim:
+    """Create, parameterise and initialise a Sim for a workload of
+    paper_1411_6697_amd.workloads (input generation only)."""
+    s = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.dvm, w.bc_x, w.bc_y, device=device, pitch=pitch)
+    s.set_params(w.R, w.gamma, 0.0, w.Q, w.omega1, w.omega2, w.m, w.n, w.T_ig)
+    F = fields if fields is not None else w.fields()
+    s.init_fields(F["rho"], F["ux"], F["uy"], F["T"], F["lam"])
+    return s

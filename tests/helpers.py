@@ -32,17 +32,29 @@ def oracle_run(w: W.Workload, steps=None, fields=None, **over):
     return P, tab, f, lam
 
 
-def max_rel_err(a: np.ndarray, b: np.ndarray, kind: str) -> float:
-    """Parity metric.  rho, T: pointwise |a-b|/|b|.  Fields that may vanish (u_x, u_y,
-    lambda): |a-b| / max(|b|, ||b||_inf); if ||b||_inf < 1e-300 the absolute error."""
+def max_rel_err(a: np.ndarray, b: np.ndarray, kind: str, scale: float = 0.0) -> float:
+    """Parity metric.  rho, T ("pointwise"): max |a-b|/|b|.  Fields that may vanish
+    ("scaled": u_x, u_y, lambda): max |a-b| / max(|b|, S) with S = max(||b||_inf, scale);
+    for the velocity components `scale` is the flow-speed scale max(||u_x||, ||u_y||) so
+    that a component that is zero up to rounding (u_y in a 1D run) is measured against
+    the flow speed.  If S < 1e-300 the absolute error is returned."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
+    if b.size == 0:
+        return 0.0
     if kind == "pointwise":
         return float(np.max(np.abs(a - b) / np.abs(b)))
-    nb = float(np.max(np.abs(b))) if b.size else 0.0
-    if nb < 1e-300:
-        return float(np.max(np.abs(a - b))) if b.size else 0.0
-    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), nb)))
+    S = max(float(np.max(np.abs(b))), float(scale))
+    if S < 1e-300:
+        return float(np.max(np.abs(a - b)))
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), S)))
 
 
 PARITY_KIND = {"rho": "pointwise", "T": "pointwise", "ux": "scaled", "uy": "scaled", "lam": "scaled"}
+
+
+def parity_errors(gpu: dict, ref: dict) -> dict:
+    """max_rel_err for rho, u_x, u_y, T, lambda with the velocity scale of `ref`."""
+    us = max(float(np.max(np.abs(np.asarray(ref["ux"])))), float(np.max(np.abs(np.asarray(ref["uy"])))))
+    return {k: max_rel_err(gpu[k], np.asarray(ref[k]), PARITY_KIND[k],
+                           us if k in ("ux", "uy") else 0.0) for k in PARITY_KIND}

@@ -1,0 +1,259 @@
+"""Parity of the HIP step (through the C ABI) with the CPU oracle, element by element.
+
+Bar: max relative error <= 1e-10 on rho, u_x, u_y, T and lambda after each run (rho, T
+pointwise; u and lambda scaled by max(|b|, ||b||_inf)).  Full configurations that the
+oracle cannot run in seconds are checked on sampled cells (the oracle advances a
+(4K+1)^2 window around each sampled cell K steps, which determines the centre cell
+exactly) and through properties that hold at any size.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1411_6697_amd import workloads as W
+from tests.helpers import PARITY_KIND, max_rel_err, oracle_init, oracle_params, oracle_run, parity_errors
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _lbkm():
+    from paper_1411_6697_amd import lbkm
+    return lbkm
+
+
+def _gpu(w, steps, fields=None, pitch=None):
+    s = _lbkm().sim_from_workload(w, fields=fields, pitch=pitch)
+    s.step(steps)
+    m = s.moments()
+    torch.cuda.synchronize()
+    return s, {k: v.cpu().numpy() for k, v in m.items()}
+
+
+def _errors(g, P, tab, f, lam):
+    om = oracle.moments(f, lam, P, tab)
+    return parity_errors(g, {k: om[k].numpy() for k in PARITY_KIND})
+
+
+def _assert_parity(g, P, tab, f, lam, tol=TOL, label=""):
+    errs = _errors(g, P, tab, f, lam)
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+
+
+def _smooth_fields(nx, ny, seed, T0=1.3, amp=0.2):
+    g = np.random.default_rng(seed)
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny)
+    ph = g.uniform(0, 2 * np.pi, 6)
+    return dict(rho=1 + amp * np.sin(2 * np.pi * X + ph[0]) * np.cos(2 * np.pi * Y + ph[1]),
+                ux=amp * np.cos(2 * np.pi * Y + ph[2]), uy=amp * np.sin(2 * np.pi * (X + Y) + ph[3]),
+                T=T0 + 0.5 * amp * np.cos(2 * np.pi * X + ph[4]) ** 2,
+                lam=0.5 + 0.4 * np.sin(2 * np.pi * X + ph[5]))
+
+
+# ---------------------------------------------------------------------------- configs
+
+def test_sod_full_config():
+    """Sod shock tube 400 x 1, 2000 steps (the full small configuration)."""
+    w = W.sod()
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    _assert_parity(g, P, tab, f, lam, label="sod")
+
+
+def test_sod_paper_rates_modification_active():
+    """The paper's literal Sod rates (R_8, R_9 != R_5, so A_hat is active)."""
+    w = W.sod(paper_rates=True, steps=800)
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    _assert_parity(g, P, tab, f, lam, label="sod-paper-rates")
+
+
+def test_detonation_reduced():
+    """1D detonation (grid, rates, DVM of the 8000 x 4 configuration) on 1200 x 4 cells for
+    1500 steps; reaction, ignition gating and lambda advection are all exercised."""
+    w = W.detonation(nx=1200, ny=4, steps=1500)
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    _assert_parity(g, P, tab, f, lam, label="detonation")
+    assert g["lam"].max() == 1.0 and 0.0 < g["lam"][0, 200:].max() < 1.0
+
+
+@pytest.mark.parametrize("reactive", [False, True])
+def test_kh_reduced(reactive):
+    """Kelvin-Helmholtz: a 96 x 128 periodic cut (rows across the lower shear layer) of the
+    2048^2 initial fields with the configuration's dx, dt and rates, 150 steps."""
+    w = W.kh(n=2048, steps=150, reactive=reactive)
+    F = {k: np.ascontiguousarray(v[448:576, 1000:1096]) for k, v in w.fields().items()}
+    w = w.with_(nx=96, ny=128)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    _assert_parity(g, P, tab, f, lam, label=f"kh-cut reactive={reactive}")
+
+
+def _window_oracle(w, fields, cells, K):
+    """Advance the oracle K steps on a (4K+1)^2 window around each cell (periodic wrap in
+    x and y) and return the centre cell's moments."""
+    r = 2 * K
+    out = []
+    for (y, x) in cells:
+        ys = [(y + d) % w.ny for d in range(-r, r + 1)]
+        xs = [(x + d) % w.nx for d in range(-r, r + 1)]
+        sub = {k: np.ascontiguousarray(v[np.ix_(ys, xs)]) for k, v in fields.items()}
+        wl = w.with_(nx=2 * r + 1, ny=2 * r + 1, bc_x="outflow", bc_y="outflow")
+        P, tab, f, lam = oracle_init(wl, fields=sub)
+        f, lam = oracle.run(f, lam, P, tab, K)
+        m = oracle.moments(f, lam, P, tab)
+        out.append({k: m[k][r, r].item() for k in ("rho", "ux", "uy", "T", "lam")})
+    return out
+
+
+@pytest.mark.parametrize("reactive", [True, False])
+def test_kh_full_size_sampled_cells(reactive):
+    """The 2048^2 Kelvin-Helmholtz configuration in the launch configuration the benchmark
+    times: 3 GPU steps, 96 sampled cells recomputed by the oracle from the same initial fields."""
+    w = W.kh(n=2048, steps=3, reactive=reactive)
+    F = w.fields()
+    s, g = _gpu(w, 3, fields=F)
+    rng = np.random.default_rng(7)
+    cells = [(int(y), int(x)) for y, x in zip(rng.integers(0, 2048, 96), rng.integers(0, 2048, 96))]
+    cells += [(0, 0), (2047, 2047), (512, 1024), (1536, 3)]
+    ref = _window_oracle(w, F, cells, 3)
+    us = max(np.abs(g["ux"]).max(), np.abs(g["uy"]).max())     # flow-speed scale of the run
+    for k in ("rho", "ux", "uy", "T", "lam"):
+        a = np.array([g[k][y, x] for (y, x) in cells])
+        b = np.array([r_[k] for r_ in ref])
+        sc = us if k in ("ux", "uy") else np.abs(g[k]).max()
+        err = max_rel_err(a, b, PARITY_KIND[k], sc)
+        print("kh2048 sampled", k, f"{err:.2e}", flush=True)
+        assert err <= TOL, (k, err)
+
+
+def test_kh_full_size_conservation_over_full_run():
+    """Inert 2048^2 Kelvin-Helmholtz, all 1000 steps: on the doubly periodic grid the NND
+    fluxes telescope and the collision conserves, so sum rho, sum rho u and sum E stay at
+    their initial values up to rounding (Eqs. moment1-moment3)."""
+    w = W.kh(n=2048, steps=1000, reactive=False)
+    s = _lbkm().sim_from_workload(w)
+    r0 = s.reduce()
+    s.step(1000)
+    r1 = s.reduce()
+    assert s.check()
+    print("kh2048 sums", r0[:4], r1[:4], flush=True)
+    assert abs(r1[0] - r0[0]) < 1e-12 * r0[0]
+    assert abs(r1[1] - r0[1]) < 1e-12 * r0[0] and abs(r1[2] - r0[2]) < 1e-12 * r0[0]
+    assert abs(r1[3] - r0[3]) < 1e-12 * r0[3]
+
+
+def test_detonation_full_size_rows_identical_and_sampled():
+    """The 8000 x 4 detonation configuration for 400 steps: the four rows stay bitwise
+    identical (y-periodic, y-uniform data), and sampled cells match the oracle."""
+    w = W.detonation(steps=400)
+    F = w.fields()
+    s, g = _gpu(w, 400, fields=F)
+    for k in g:
+        assert np.array_equal(g[k][0], g[k][3]) and np.array_equal(g[k][1], g[k][2])
+    # the oracle on the first 1800 cells (outflow at x = 0 is exact there; the cut at
+    # x = 1800 is 1600 cells = 4 steps x 400 ahead of the checked region)
+    w1 = w.with_(nx=1800, ny=1)
+    F1 = {k: v[:1, :1800] for k, v in F.items()}
+    P, tab, f, lam = oracle_init(w1, fields=F1)
+    f, lam = oracle.run(f, lam, P, tab, 400)
+    om = oracle.moments(f, lam, P, tab)
+    errs = parity_errors({k: g[k][0, :200] for k in PARITY_KIND}, {k: om[k][0, :200].numpy() for k in PARITY_KIND})
+    print("det8000 left", errs, flush=True)
+    for k, e in errs.items():
+        assert e <= TOL, (k, e)
+
+
+# ---------------------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("nx,ny,bcx,bcy", [(67, 5, "outflow", "outflow"), (1, 1, "periodic", "periodic"),
+                                           (1, 9, "outflow", "periodic"), (130, 3, "periodic", "outflow"),
+                                           (3, 70, "periodic", "periodic"), (2, 2, "outflow", "periodic")])
+def test_ragged_and_degenerate_grids(nx, ny, bcx, bcy):
+    """Tiles that do not divide the grid, single-cell axes, both boundary rules on both
+    axes, with the reaction, A_hat and lambda advection active."""
+    w = W.Workload(name="edge", nx=nx, ny=ny, dx=2e-3, dy=1.5e-3, dt=1e-5, steps=40,
+                   dvm=W.DVM_UNSTEADY_DET, gamma=1.4, I=3.0, R=W.rates(5e3, r8=1e4, r9=2.5e3),
+                   Q=0.8, omega1=2.0, omega2=100.0, bc_x=bcx, bc_y=bcy)
+    F = _smooth_fields(nx, ny, seed=nx * 100 + ny)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    _assert_parity(g, P, tab, f, lam, label=f"edge {nx}x{ny}")
+
+
+def test_larger_pitch_gives_bitwise_identical_results():
+    w = W.sod(nx=200, steps=100)
+    _, a = _gpu(w, 100)
+    _, b = _gpu(w, 100, pitch=200 + 96)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_runs_are_deterministic_and_resume_bitwise():
+    """Two runs agree bitwise; N steps, save, restore, N steps equals 2N steps bitwise."""
+    w = W.detonation(nx=600, ny=4, steps=0)
+    s1, _ = _gpu(w, 0)
+    s1.step(200)
+    f, lam = s1.get_state()
+    s1.step(200)
+    a = s1.moments()
+    s2, _ = _gpu(w, 400)
+    b = s2.moments()
+    s3 = _lbkm().sim_from_workload(w)
+    s3.set_state(f, lam)
+    s3.step(200)
+    c = s3.moments()
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k])
+    assert s1.step_count() == 400 and s3.step_count() == 200
+
+
+# ---------------------------------------------------------------------------- readouts
+
+def test_tne_and_reductions_match_oracle():
+    w = W.detonation(nx=700, ny=4, steps=300).with_(R=W.rates(100.0, r8=200.0, r9=150.0))
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    delta, d = s.tne()
+    do, dd = oracle.tne(f, P, tab)
+    # Delta_k = f_hat_k - f_hat^eq_k is a difference of moments, so its rounding error is set
+    # by the size of the moment: compare at 1e-10 of max(|Delta_k|, ||f_hat^eq_k||_inf)
+    m = oracle.moments(f, lam, P, tab)
+    feq = oracle.equilibrium_moments(m["rho"], m["ux"], m["uy"], m["T"], P.I)[4:]
+    scale = torch.maximum(do.abs(), feq.abs().amax(dim=(1, 2), keepdim=True))
+    err = ((delta.cpu() - do).abs() / scale).max().item()
+    print("tne err", err, flush=True)
+    assert err <= 1e-10
+    assert torch.allclose(d.cpu(), dd, rtol=1e-8, atol=1e-10 * feq.abs().max().item())
+    r = s.reduce()
+    ro = oracle.reductions(f, lam, P, tab).numpy()
+    print("reduce", r, ro, flush=True)
+    assert np.allclose(r[[0, 3]], ro[[0, 3]], rtol=1e-12)
+    assert abs(r[1] - ro[1]) < 1e-10 * ro[0] and abs(r[2] - ro[2]) < 1e-10 * ro[0]
+    assert np.allclose(r[4:6], ro[4:6], rtol=1e-8)
+    assert r[6] == ro[6] or abs(r[6] - ro[6]) < 1e-12
+    assert abs(r[7] - ro[7]) < 1e-12
+
+
+def test_check_flags_nonfinite_and_nonpositive_states():
+    w = W.sod(nx=64, steps=0)
+    s, _ = _gpu(w, 0)
+    assert s.check()
+    f, lam = s.get_state()
+    bad = f.clone()
+    bad[3, 0, 10] = float("nan")
+    s.set_state(bad, lam)
+    assert not s.check()
+    neg = f.clone() * -1.0                      # rho < 0 everywhere
+    s.set_state(neg, lam)
+    assert not s.check()
+    s.set_state(f, lam)
+    assert s.check()
