@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 BYTES_PER_CELL = 400            # 24 f read + 24 f written + lambda read + lambda written, 8 B each
 PMC_FILE = os.path.join(ROOT, "profiles", "k_step_kh2048_pmc.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1411_6697_amd", "csrc", n)
-                  for n in ("kernels.hip", "lbkm_device.h", "lbkm_internal.h")]
+                  for n in ("step.hip", "lbkm_device.h", "lbkm_internal.h")]
 
 
 def kernel_source_hash() -> str:

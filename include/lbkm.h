@@ -137,6 +137,11 @@ lbkm_status lbkm_check(lbkm_ctx* ctx);
 lbkm_status lbkm_get_state(lbkm_ctx* ctx, double* f, double* lam);
 lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam);
 
+/* Work-group tile of the step kernel, tile_x x tile_y cells.  Compiled shapes: 256x2
+ * (default), 256x1, 128x2, 64x4; LBKM_EINVAL for any other.  Results do not depend on
+ * the tile. */
+lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y);
+
 /* Host copies of the dense 24x24 moment matrix M (row k = moment m_{k+1}, column i =
  * velocity i) and of M^-1, both row-major, reassembled from the symmetry blocks the
  * kernels use; *cond (may be NULL) receives ||M||_inf ||M^-1||_inf.  Needs no device. */

@@ -230,7 +230,7 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     if (n < 0) return fail(ctx, LBKM_EINVAL, "n must be >= 0");
     for (int64_t k = 0; k < n; ++k) {
         const int a = ctx->cur, b = 1 - a;
-        hipError_t e = launch_step(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[a], ctx->f[b], ctx->lam[a],
+        hipError_t e = launch_step(ctx->d, ctx->step_variant, step_flags(ctx->h), ctx->grid.nx, ctx->grid.ny, ctx->f[a], ctx->f[b], ctx->lam[a],
                                    ctx->lam[b], ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
         ctx->cur = b;
@@ -306,6 +306,16 @@ lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam) {
     ctx->fields = true;
     ctx->steps = 0;
     return LBKM_OK;
+}
+
+lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y) {
+    if (!ctx) return LBKM_EINVAL;
+    for (int v = 0; v < kNumStepVariants; ++v)
+        if (kStepVariants[v][0] == tile_x && kStepVariants[v][1] == tile_y) {
+            ctx->step_variant = v;
+            return LBKM_OK;
+        }
+    return fail(ctx, LBKM_EINVAL, "unsupported step tile shape");
 }
 
 lbkm_status lbkm_get_matrices(lbkm_ctx* ctx, double* M, double* Minv, double* cond) {

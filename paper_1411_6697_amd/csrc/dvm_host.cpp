@@ -121,20 +121,20 @@ int build_moment_blocks(const double dvm[6], Consts* c, double* cond) {
     auto fac_2 = [](int row) { return (row % 2 == 1) ? 0.25L : 0.5L; };
     for (int r = 0; r < NEE; ++r)
         for (int k = 0; k < NEE; ++k) {
-            c->BEE[r][k] = (double)bee[r * NEE + k];
-            c->CEE[r][k] = (double)(fac_ee(r) * iee[r * NEE + k]);
+            c->mat.BEE[k][r] = (double)bee[r * NEE + k];
+            c->mat.CEE[k][r] = (double)(fac_ee(r) * iee[r * NEE + k]);
         }
     for (int r = 0; r < NOE; ++r)
         for (int k = 0; k < NOE; ++k) {
-            c->BOE[r][k] = (double)boe[r * NOE + k];
-            c->COE[r][k] = (double)(fac_2(r) * ioe[r * NOE + k]);
-            c->BEO[r][k] = (double)beo[r * NEO + k];
-            c->CEO[r][k] = (double)(fac_2(r) * ieo[r * NEO + k]);
+            c->mat.BOE[k][r] = (double)boe[r * NOE + k];
+            c->mat.COE[k][r] = (double)(fac_2(r) * ioe[r * NOE + k]);
+            c->mat.BEO[k][r] = (double)beo[r * NEO + k];
+            c->mat.CEO[k][r] = (double)(fac_2(r) * ieo[r * NEO + k]);
         }
     for (int r = 0; r < NOO; ++r)
         for (int k = 0; k < NOO; ++k) {
-            c->BOO[r][k] = (double)boo[r * NOO + k];
-            c->COO[r][k] = (double)(0.25L * ioo[r * NOO + k]);
+            c->mat.BOO[k][r] = (double)boo[r * NOO + k];
+            c->mat.COO[k][r] = (double)(0.25L * ioo[r * NOO + k]);
         }
     // condition estimate of the dense M: ||M||_inf ||M^-1||_inf
     double Md[NV * NV], Mi[NV * NV];
@@ -167,25 +167,25 @@ void dense_from_blocks(const Consts* c, double* M, double* Minv) {
             for (int s = 0; s < 3; ++s)
                 if (sEE[s][d])
                     for (int r = 0; r < NEE; ++r) {
-                        M[EE_M[r] * NV + i] = sEE[s][d] * c->BEE[r][3 * g + s];
-                        Minv[i * NV + EE_M[r]] += sEE[s][d] * c->CEE[3 * g + s][r];
+                        M[EE_M[r] * NV + i] = sEE[s][d] * c->mat.BEE[3 * g + s][r];
+                        Minv[i * NV + EE_M[r]] += sEE[s][d] * c->mat.CEE[r][3 * g + s];
                     }
             for (int s = 0; s < 2; ++s) {
                 if (sOE[s][d])
                     for (int r = 0; r < NOE; ++r) {
-                        M[OE_M[r] * NV + i] = sOE[s][d] * c->BOE[r][2 * g + s];
-                        Minv[i * NV + OE_M[r]] += sOE[s][d] * c->COE[2 * g + s][r];
+                        M[OE_M[r] * NV + i] = sOE[s][d] * c->mat.BOE[2 * g + s][r];
+                        Minv[i * NV + OE_M[r]] += sOE[s][d] * c->mat.COE[r][2 * g + s];
                     }
                 if (sEO[s][d])
                     for (int r = 0; r < NEO; ++r) {
-                        M[EO_M[r] * NV + i] = sEO[s][d] * c->BEO[r][2 * g + s];
-                        Minv[i * NV + EO_M[r]] += sEO[s][d] * c->CEO[2 * g + s][r];
+                        M[EO_M[r] * NV + i] = sEO[s][d] * c->mat.BEO[2 * g + s][r];
+                        Minv[i * NV + EO_M[r]] += sEO[s][d] * c->mat.CEO[r][2 * g + s];
                     }
             }
             if (sOO[0][d])
                 for (int r = 0; r < NOO; ++r) {
-                    M[OO_M[r] * NV + i] = sOO[0][d] * c->BOO[r][g];
-                    Minv[i * NV + OO_M[r]] += sOO[0][d] * c->COO[g][r];
+                    M[OO_M[r] * NV + i] = sOO[0][d] * c->mat.BOO[g][r];
+                    Minv[i * NV + OO_M[r]] += sOO[0][d] * c->mat.COO[r][g];
                 }
         }
 }

@@ -1,8 +1,7 @@
 // HIP kernels of the single-grid MRT-LBKM path (gfx950, float64) and their launchers.
 //
-// State layout (structure of arrays): f[24][ny][pitch], lambda[ny][pitch].  One thread
-// updates one cell; a work-group covers a 64 x 4 tile so that each wavefront reads 64
-// consecutive cells of a row (512 contiguous bytes per velocity plane).
+// Initialisation, readouts, reductions and copies.  State layout (structure of arrays):
+// f[24][ny][pitch], lambda[ny][pitch].  The step kernel lives in step.hip.
 
 #include <hip/hip_runtime.h>
 
@@ -13,94 +12,10 @@ namespace lbkm {
 
 namespace {
 
-constexpr int TX = 64, TY = 4;
-
-struct Idx {
-    int64_t c, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2;   // element offsets in one plane
-};
-
-__device__ __forceinline__ Idx stencil_index(const Consts* __restrict__ c, int x, int y) {
-    const int nx = c->nx, ny = c->ny;
-    const int64_t p = c->pitch;
-    const int64_t row = (int64_t)y * p;
-    Idx s;
-    s.c = row + x;
-    s.xm2 = row + wrap(x - 2, nx, c->bc_x);
-    s.xm1 = row + wrap(x - 1, nx, c->bc_x);
-    s.xp1 = row + wrap(x + 1, nx, c->bc_x);
-    s.xp2 = row + wrap(x + 2, nx, c->bc_x);
-    s.ym2 = (int64_t)wrap(y - 2, ny, c->bc_y) * p + x;
-    s.ym1 = (int64_t)wrap(y - 1, ny, c->bc_y) * p + x;
-    s.yp1 = (int64_t)wrap(y + 1, ny, c->bc_y) * p + x;
-    s.yp2 = (int64_t)wrap(y + 2, ny, c->bc_y) * p + x;
-    return s;
-}
-
 __device__ __forceinline__ void load_cell(const double* __restrict__ f, int64_t plane, int64_t at,
                                           double v[NV]) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = f[i * plane + at];
-}
-
-// one full time step for every cell (Sec. II; all inputs at level n)
-__global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c,
-                                                  const double* __restrict__ fin,
-                                                  double* __restrict__ fout,
-                                                  const double* __restrict__ lin,
-                                                  double* __restrict__ lout) {
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y * TY + threadIdx.y;
-    if (x >= c->nx || y >= c->ny) return;
-    const int64_t plane = c->plane;
-    const Idx s = stencil_index(c, x, y);
-
-    double f[NV];
-    load_cell(fin, plane, s.c, f);
-    Blocks sb, h;
-    to_combos(f, sb);
-    forward(c, sb, h);
-    const Macro m = macro_of(h, c->DI);
-
-    double A8 = 0.0, A9 = 0.0;
-    if (c->amod) {
-        double nb[NV], uxe, uye, uxw, uyw, uxn, uyn, uxs, uys;
-        load_cell(fin, plane, s.xp1, nb);
-        velocity_of(c, nb, uxe, uye);
-        load_cell(fin, plane, s.xm1, nb);
-        velocity_of(c, nb, uxw, uyw);
-        load_cell(fin, plane, s.yp1, nb);
-        velocity_of(c, nb, uxn, uyn);
-        load_cell(fin, plane, s.ym1, nb);
-        velocity_of(c, nb, uxs, uys);
-        modification(c, m, (uxe - uxw) * c->half_inv_dx, (uxn - uxs) * c->half_inv_dy,
-                     (uye - uyw) * c->half_inv_dx, (uyn - uys) * c->half_inv_dy, A8, A9);
-    }
-
-    const double lam = lin[s.c];
-    double src[NV], dlam;
-    local_source(c, f, lam, A8, A9, m, h, src, dlam);
-
-    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double v = c->vg[g];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int i = 8 * g + d;
-            const double* b = fin + i * plane;
-            double adv = 0.0;
-            if (DUX[d] > 0) adv += v * (nnd_pos(b[s.xm2], b[s.xm1], f[i], b[s.xp1]) * idx_);
-            if (DUX[d] < 0) adv -= v * (nnd_neg(b[s.xm1], f[i], b[s.xp1], b[s.xp2]) * idx_);
-            if (DUY[d] > 0) adv += v * (nnd_pos(b[s.ym2], b[s.ym1], f[i], b[s.yp1]) * idy);
-            if (DUY[d] < 0) adv -= v * (nnd_neg(b[s.ym1], f[i], b[s.yp1], b[s.yp2]) * idy);
-            fout[i * plane + s.c] = f[i] + dt * (src[i] - adv);
-        }
-    }
-    const double dlx = (m.ux > 0.0) ? nnd_pos(lin[s.xm2], lin[s.xm1], lam, lin[s.xp1])
-                                    : nnd_neg(lin[s.xm1], lam, lin[s.xp1], lin[s.xp2]);
-    const double dly = (m.uy > 0.0) ? nnd_pos(lin[s.ym2], lin[s.ym1], lam, lin[s.yp1])
-                                    : nnd_neg(lin[s.ym1], lam, lin[s.yp1], lin[s.yp2]);
-    lout[s.c] = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
 }
 
 // f = M^-1 f_hat^eq(rho, u, T) (Eq. moment12), lambda copied; inputs dense [ny][nx]
@@ -306,13 +221,6 @@ __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, d
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-
-hipError_t launch_step(const Consts* dc, int nx, int ny, const double* fin, double* fout,
-                       const double* lin, double* lout, hipStream_t st) {
-    dim3 grid((nx + TX - 1) / TX, (ny + TY - 1) / TY), block(TX, TY);
-    hipLaunchKernelGGL(k_step, grid, block, 0, st, dc, fin, fout, lin, lout);
-    return hipGetLastError();
-}
 
 static dim3 row_grid(int nx, int ny) { return dim3((nx + 255) / 256, ny); }
 

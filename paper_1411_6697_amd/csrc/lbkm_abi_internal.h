@@ -22,6 +22,7 @@ struct lbkm_ctx {
     double* lam[2] = {nullptr, nullptr};
     int64_t pitch = 0;
     int cur = 0;
+    int step_variant = 0;              // tile shape of the step kernel (kStepVariants)
     bool bound = false, params = false, fields = false;
     int64_t steps = 0;
     double cond = 0.0;

@@ -57,31 +57,68 @@ __device__ __forceinline__ void from_combos(const Blocks& s, double f[NV]) {
     }
 }
 
+// Make the (scalar) pointer p depend on the N values y: loads through p cannot be issued
+// before y is computed.
 template <int N>
-__device__ __forceinline__ void matvec(const double (*A)[N], const double* x, double* y) {
+__device__ __forceinline__ void tie_after(const double*& p, const double* y) {
+    if constexpr (N == 9)
+        asm volatile("" : "+s"(p) : "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(y[3]), "v"(y[4]), "v"(y[5]),
+                     "v"(y[6]), "v"(y[7]), "v"(y[8]));
+    else if constexpr (N == 6)
+        asm volatile("" : "+s"(p) : "v"(y[0]), "v"(y[1]), "v"(y[2]), "v"(y[3]), "v"(y[4]), "v"(y[5]));
+    else
+        asm volatile("" : "+s"(p) : "v"(y[0]), "v"(y[1]), "v"(y[2]));
+}
+
+// y = A x with A stored column-major (At[k][r] = A[r][k]).  The loop runs over columns:
+// the N accumulators are independent multiply-add chains, and each column's N constants
+// (one scalar load) are consumed right after they arrive, so few of the 324 matrix entries
+// are held in scalar registers at a time.  Each y[r] still sums over k in increasing order.
+template <int N>
+__device__ __forceinline__ void matvec(const double (*At)[N], const double* x, double* y) {
+    // A fresh (opaque) copy of the matrix address per product: the inverse blocks are used
+    // twice per cell, and letting the compiler share their loads keeps 162 doubles in
+    // scalar registers between the two uses (and spills them).
+    // The copy is read through the constant address space, which the kernel never writes,
+    // so the loads stay scalar.
+    // Tying the copy to the input vector also keeps these loads from being hoisted ahead of
+    // the code that produces x, and each column's address is tied to all results of the
+    // previous column, so one column (<= 18 scalar registers) is in flight at a time.
+    asm volatile("" : "+s"(At) : "v"(x[N - 1]));
+    typedef const __attribute__((address_space(4))) double cdouble;
+    cdouble* A = (cdouble*)(const void*)At;
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        double acc = 0.0;
+    for (int r = 0; r < N; ++r) y[r] = A[r] * x[0];
 #pragma unroll
-        for (int k = 0; k < N; ++k) acc = fma(A[r][k], x[k], acc);
-        y[r] = acc;
+    for (int k = 1; k < N; ++k) {
+        const double* col = At[k];
+        tie_after<N>(col, y);
+        cdouble* Ak = (cdouble*)(const void*)col;
+#pragma unroll
+        for (int r = 0; r < N; ++r) y[r] = fma(Ak[r], x[k], y[r]);
     }
 }
 
-// f_hat = M f in block order
+// f_hat = M f in block order (M from global constants or from an LDS copy)
+__device__ __forceinline__ void forward(const Mats& M, const Blocks& s, Blocks& h) {
+    matvec<NEE>(M.BEE, s.ee, h.ee);
+    matvec<NOE>(M.BOE, s.oe, h.oe);
+    matvec<NEO>(M.BEO, s.eo, h.eo);
+    matvec<NOO>(M.BOO, s.oo, h.oo);
+}
 __device__ __forceinline__ void forward(const Consts* __restrict__ c, const Blocks& s, Blocks& h) {
-    matvec<NEE>(c->BEE, s.ee, h.ee);
-    matvec<NOE>(c->BOE, s.oe, h.oe);
-    matvec<NEO>(c->BEO, s.eo, h.eo);
-    matvec<NOO>(c->BOO, s.oo, h.oo);
+    forward(c->mat, s, h);
 }
 
 // combination values of M^-1 g
+__device__ __forceinline__ void inverse(const Mats& M, const Blocks& g, Blocks& s) {
+    matvec<NEE>(M.CEE, g.ee, s.ee);
+    matvec<NOE>(M.COE, g.oe, s.oe);
+    matvec<NEO>(M.CEO, g.eo, s.eo);
+    matvec<NOO>(M.COO, g.oo, s.oo);
+}
 __device__ __forceinline__ void inverse(const Consts* __restrict__ c, const Blocks& g, Blocks& s) {
-    matvec<NEE>(c->CEE, g.ee, s.ee);
-    matvec<NOE>(c->COE, g.oe, s.oe);
-    matvec<NEO>(c->CEO, g.eo, s.eo);
-    matvec<NOO>(c->COO, g.oo, s.oo);
+    inverse(c->mat, g, s);
 }
 
 // Equilibrium moments f_hat^eq (Sec. II closed forms, factor T in entries 14 and 16 as
@@ -163,9 +200,11 @@ __device__ __forceinline__ void velocity_of(const Consts* __restrict__ c, const 
     uy = jy / rho;
 }
 
-// minmod: the argument of smaller magnitude if both have the same strict sign, else 0
+// minmod: the argument of smaller magnitude if both have the same strict sign, else 0.
+// That is the median of (a, b, 0), computed branch-free and exactly as
+// max(min(a,b), min(max(a,b), 0)).
 __device__ __forceinline__ double minmod(double a, double b) {
-    return (a > 0.0 && b > 0.0) ? fmin(a, b) : ((a < 0.0 && b < 0.0) ? fmax(a, b) : 0.0);
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
 }
 
 // NND differences h_{j+1/2} - h_{j-1/2} (to be divided by the spacing), Zhang 1988,
@@ -183,11 +222,19 @@ __device__ __forceinline__ double nnd_neg(double fm1, double f0, double fp1, dou
 
 // Cochran increment of lambda over one step, p frozen (exact solution of the Bernoulli
 // equation d(1-lambda)/dt = -(1-lambda)(a + b lambda)); zero unless T > T_ig,
-// lambda < 1 and a + b > 0.
+// lambda < 1 and a + b > 0.  CHEM = false compiles the reaction out (omega1 = omega2 = 0);
+// GEXP = false assumes m = n = 1 (the paper's choice), so p^m = p without a pow call.
+template <bool CHEM = true, bool GEXP = true>
 __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double lam, double p, double T) {
-    if (!c->chem) return 0.0;
-    const double a = c->w1 * (c->m_is_one ? p : pow(p, c->pm));
-    const double b = c->w2 * (c->n_is_one ? p : pow(p, c->pn));
+    if (!CHEM || !c->chem) return 0.0;
+    double a, b;
+    if (GEXP) {
+        a = c->w1 * (c->m_is_one ? p : pow(p, c->pm));
+        b = c->w2 * (c->n_is_one ? p : pow(p, c->pn));
+    } else {
+        a = c->w1 * p;
+        b = c->w2 * p;
+    }
     const double cc = a + b;
     if (!(T > c->Tig && lam < 1.0 && cc > 0.0)) return 0.0;
     const double y0 = 1.0 - lam;
@@ -197,41 +244,53 @@ __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double l
 }
 
 // Collision and chemistry of one cell.
-// Input: f (24 values of the cell), lam, A8/A9 (modification terms, 0 if inactive).
-// Output: src[i] = -Omega_i + C_i (the non-streaming right-hand side) and dlam.
-__device__ __forceinline__ void local_source(const Consts* __restrict__ c, const double f[NV],
-                                             double lam, double A8, double A9, const Macro& m,
-                                             const Blocks& h, double src[NV], double& dlam) {
-    Blocks e;
-    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
-    // g = R (f_hat - f_hat^eq) - A_hat, Delta_1..4 = 0
-    Blocks g;
+// Input: the macroscopic state m, the moments h = M f of the cell, lam, A8/A9 (modification
+// terms, 0 if inactive).  Output: src[i] = -Omega_i + C_i (the non-streaming right-hand
+// side) and dlam.  Ordered to keep few 24-vectors live: g = R (h - f_hat^eq) - A_hat
+// (h and f_hat^eq die), src = -M^-1 g (g dies), then f_hat^eq is evaluated again for
+// C_i = f^eq_i w_i with f^eq = M^-1 f_hat^eq.
+template <bool CHEM = true, bool GEXP = true>
+__device__ __forceinline__ void local_source(const Consts* __restrict__ c, const Mats& M, double lam,
+                                             double A8, double A9, const Macro& m, const Blocks& h,
+                                             double src[NV], double& dlam) {
+    {
+        Blocks e;
+        equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+        // g = R (f_hat - f_hat^eq) - A_hat, Delta_1..4 = 0
+        Blocks g;
 #pragma unroll
-    for (int r = 0; r < NEE; ++r) g.ee[r] = c->R[EE_M[r]] * (h.ee[r] - e.ee[r]);
+        for (int r = 0; r < NEE; ++r) g.ee[r] = c->R[EE_M[r]] * (h.ee[r] - e.ee[r]);
 #pragma unroll
-    for (int r = 0; r < NOE; ++r) g.oe[r] = c->R[OE_M[r]] * (h.oe[r] - e.oe[r]);
+        for (int r = 0; r < NOE; ++r) g.oe[r] = c->R[OE_M[r]] * (h.oe[r] - e.oe[r]);
 #pragma unroll
-    for (int r = 0; r < NEO; ++r) g.eo[r] = c->R[EO_M[r]] * (h.eo[r] - e.eo[r]);
+        for (int r = 0; r < NEO; ++r) g.eo[r] = c->R[EO_M[r]] * (h.eo[r] - e.eo[r]);
 #pragma unroll
-    for (int r = 0; r < NOO; ++r) g.oo[r] = c->R[OO_M[r]] * (h.oo[r] - e.oo[r]);
-    g.ee[0] = 0.0;   // m1
-    g.ee[1] = 0.0;   // m4
-    g.oe[0] = 0.0;   // m2
-    g.eo[0] = 0.0;   // m3
-    g.oe[1] -= A8;   // m8
-    g.eo[1] -= A9;   // m9
-    Blocks s;
-    inverse(c, g, s);
-    double om[NV];
-    from_combos(s, om);
+        for (int r = 0; r < NOO; ++r) g.oo[r] = c->R[OO_M[r]] * (h.oo[r] - e.oo[r]);
+        g.ee[0] = 0.0;   // m1
+        g.ee[1] = 0.0;   // m4
+        g.oe[0] = 0.0;   // m2
+        g.eo[0] = 0.0;   // m3
+        g.oe[1] -= A8;   // m8
+        g.eo[1] -= A9;   // m9
+        Blocks s;
+        inverse(M, g, s);
+        double om[NV];
+        from_combos(s, om);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) src[i] = -om[i];
-
-    dlam = cochran(c, lam, m.rho * m.T, m.T);
-    if (dlam != 0.0) {
-        // C_i = f^eq_i Q [-(1+D) I T + I |v_i - u|^2 + eta_i^2] F / (I (D+I) T^2), F = dlam/dt
+        for (int i = 0; i < NV; ++i) src[i] = -om[i];
+    }
+    dlam = cochran<CHEM, GEXP>(c, lam, m.rho * m.T, m.T);
+    if (CHEM && dlam != 0.0) {
+        // C_i = f^eq_i Q [-(1+D) I T + I |v_i - u|^2 + eta_i^2] F / (I (D+I) T^2), F = dlam/dt.
+        // f_hat^eq is evaluated again (from an opaque copy of T, so the compiler does not
+        // reuse the first evaluation) rather than kept live through the collision.
+        __builtin_amdgcn_sched_barrier(0);
+        double T2 = m.T;
+        asm volatile("" : "+v"(T2));
+        Blocks e2;
+        equilibrium(m.rho, m.ux, m.uy, T2, c->I, e2);
         Blocks se;
-        inverse(c, e, se);
+        inverse(M, e2, se);
         double feq[NV];
         from_combos(se, feq);
         const double F = dlam / c->dt;

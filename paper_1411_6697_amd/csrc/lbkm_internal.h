@@ -19,13 +19,20 @@ constexpr int NV = 24;     // D2V24: 3 groups x 8 directions (Sec. II)
 //   EO: m3 m9 m11 m13 m22 m24               OO: m6 m15 m18
 constexpr int NEE = 9, NOE = 6, NEO = 6, NOO = 3;
 
-struct Consts {
-    double vg[3];                 // group speeds v_a, v_b, v_c
-    double eta2[3];               // eta_g^2
+// The moment-matrix blocks, each stored column-major (X[k][r] is row r, column k) so that
+// a kernel reads one column with one scalar load.
+struct Mats {
     // forward blocks: f_hat(class) = B(class) * s(class), s = symmetric combinations
     double BEE[NEE][NEE], BOE[NOE][NOE], BEO[NEO][NEO], BOO[NOO][NOO];
     // inverse blocks with the 1/2 (axis) and 1/4 (diagonal) recombination factors folded in
     double CEE[NEE][NEE], COE[NOE][NOE], CEO[NEO][NEO], COO[NOO][NOO];
+};
+constexpr int kMatsDoubles = sizeof(Mats) / sizeof(double);
+
+struct Consts {
+    Mats mat;
+    double vg[3];                 // group speeds v_a, v_b, v_c
+    double eta2[3];               // eta_g^2
     double R[NV];                 // R_1..R_24
     double I, DI;                 // I and D + I
     double Q, w1, w2, pm, pn, Tig;

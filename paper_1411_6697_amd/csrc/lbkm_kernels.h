@@ -7,8 +7,11 @@
 
 namespace lbkm {
 
-hipError_t launch_step(const Consts* dc, int nx, int ny, const double* fin, double* fout,
-                       const double* lin, double* lout, hipStream_t st);
+extern const int kStepVariants[][2];   // {tile_x, tile_y} per launch variant (step.hip)
+extern const int kNumStepVariants;
+int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
+hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
+                       double* fout, const double* lin, double* lout, hipStream_t st);
 hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,
                        const double* uy, const double* T, const double* lam, double* f, double* lout,
                        hipStream_t st);

@@ -1,0 +1,236 @@
+// The fused MRT-LBKM time step (gfx950, float64).
+//
+// One thread advances one cell through the whole step of Sec. II: macroscopic moments,
+// f_hat = M f, equilibrium, A_hat (when active), collision, chemistry and C_i, M^-1,
+// NND streaming of all 24 planes, forward Euler, and the lambda update.  All inputs are
+// read at level n from `fin`/`lin`; results go to the other buffer pair.
+//
+// Instruction economy (the kernel is issue-bound unless this is watched):
+//  - the 324 moment-matrix entries are read column by column with scalar loads and
+//    consumed at once (column-major matrix-vector products);
+//  - the state is read through buffer resources: plane i of a cell is the scalar offset
+//    i * plane_bytes plus the cell's 32-bit byte offset, which is the same for all 24
+//    planes, so loads need no per-load address arithmetic;
+//  - minmod is branch-free (four min/max).
+//
+// Work-groups cover TX x TY tiles.  The hardware hands consecutive work-group ids to the
+// eight XCDs in turn; `tile_of` renumbers tiles so that XCD k walks the k-th contiguous
+// band of tiles in row-major order, keeping halo re-reads inside one XCD's L2.
+
+#include <hip/hip_runtime.h>
+
+#include "lbkm_device.h"
+#include "lbkm_kernels.h"
+
+namespace lbkm {
+
+namespace {
+
+constexpr int kXcds = 8;
+
+// byte offsets (within one plane) of a cell and its stencil neighbours
+struct Off {
+    uint32_t c, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2;
+};
+
+__device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int x, int y) {
+    const int nx = c->nx, ny = c->ny;
+    const uint32_t p = (uint32_t)c->pitch;
+    const uint32_t row = (uint32_t)y * p;
+    Off s;
+    s.c = (row + x) * 8u;
+    s.xm2 = (row + wrap(x - 2, nx, c->bc_x)) * 8u;
+    s.xm1 = (row + wrap(x - 1, nx, c->bc_x)) * 8u;
+    s.xp1 = (row + wrap(x + 1, nx, c->bc_x)) * 8u;
+    s.xp2 = (row + wrap(x + 2, nx, c->bc_x)) * 8u;
+    s.ym2 = ((uint32_t)wrap(y - 2, ny, c->bc_y) * p + x) * 8u;
+    s.ym1 = ((uint32_t)wrap(y - 1, ny, c->bc_y) * p + x) * 8u;
+    s.yp1 = ((uint32_t)wrap(y + 1, ny, c->bc_y) * p + x) * 8u;
+    s.yp2 = ((uint32_t)wrap(y + 2, ny, c->bc_y) * p + x) * 8u;
+    return s;
+}
+
+// A structure-of-arrays buffer seen through one buffer resource: plane i of a cell is at
+// byte offset i * plane_bytes (scalar offset operand) + the cell's byte offset (vector
+// operand).  The whole buffer must lie within 4 GiB of its base.
+struct Soa {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t plane_bytes;
+};
+
+__device__ __forceinline__ Soa soa(const double* base, int64_t plane) {
+    Soa s;
+    s.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, -1, 0x00020000);
+    s.plane_bytes = (uint32_t)(plane * 8);
+    return s;
+}
+
+// load/store at scalar byte offset `soff` (e.g. a plane) plus vector byte offset `voff`
+__device__ __forceinline__ double ld(const Soa& b, uint32_t soff, uint32_t voff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void st(const Soa& b, uint32_t soff, uint32_t voff, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 0);
+}
+
+// An opaque copy of a wave-uniform value.  Offsets derived from different copies are not
+// merged by the compiler, so the 24 plane offsets of one phase are not kept alive (and
+// spilled) through the other phase.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// the 24 values of one cell; the plane step is added to the vector offset
+__device__ __forceinline__ void load_cell(const Soa& f, uint32_t off, double v[NV]) {
+    const uint32_t pb = opaque(f.plane_bytes);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        v[i] = ld(f, 0u, off);
+        off += pb;
+    }
+}
+
+// one full time step of one cell (all inputs at level n); M holds the matrix blocks.
+// AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1.
+template <bool AMOD, bool CHEM, bool GEXP>
+__device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Mats& M, int x, int y,
+                                          const double* __restrict__ fin, double* __restrict__ fout,
+                                          const double* __restrict__ lin, double* __restrict__ lout) {
+    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
+    const Soa L = soa(lin, 0), Lo = soa(lout, 0);
+    const Off s = stencil_offsets(c, x, y);
+
+    // Phase 1: collision and chemistry from the 24 centre values -> src = -Omega + C.
+    double src[NV], dlam, lam;
+    Macro m;
+    {
+        // velocity gradients for A_hat first, so only four numbers are carried on
+        double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
+        if (AMOD) {
+            double nb[NV], ua, va, ub, vb;
+            load_cell(F, s.xp1, nb);
+            velocity_of(c, nb, ua, va);
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.xm1, nb);
+            velocity_of(c, nb, ub, vb);
+            gxx = (ua - ub) * c->half_inv_dx;          // d u_x / dx
+            gyx = (va - vb) * c->half_inv_dx;          // d u_y / dx
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.yp1, nb);
+            velocity_of(c, nb, ua, va);
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.ym1, nb);
+            velocity_of(c, nb, ub, vb);
+            gxy = (ua - ub) * c->half_inv_dy;          // d u_x / dy
+            gyy = (va - vb) * c->half_inv_dy;          // d u_y / dy
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double f[NV];
+        load_cell(F, s.c, f);
+        Blocks sb, h;
+        to_combos(f, sb);
+        forward(M, sb, h);
+        m = macro_of(h, c->DI);
+        double A8 = 0.0, A9 = 0.0;
+        if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
+        lam = ld(L, 0u, s.c);
+        local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // Phase 2: NND streaming plane by plane; the centre value is read again (a cache hit)
+    // so that only src[] stays live across the planes.
+    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+    const uint32_t pb = opaque(F.plane_bytes);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double v = c->vg[g];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t so = (uint32_t)(8 * g + d) * pb;
+            const double f0 = ld(F, so, s.c);
+            double adv = 0.0;
+            if (DUX[d] > 0) adv += v * (nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)) * idx_);
+            if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)) * idx_);
+            if (DUY[d] > 0) adv += v * (nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)) * idy);
+            if (DUY[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)) * idy);
+            st(G, so, s.c, f0 + dt * (src[8 * g + d] - adv));
+        }
+    }
+    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
+                                    : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
+    const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
+                                    : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
+    st(Lo, 0u, s.c, lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+}
+
+// tile t of the XCD-aware order for work-group b; returns false past the last tile
+__device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int& tx, int& ty) {
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    const int t = (b % kXcds) * per + b / kXcds;
+    if (t >= ntiles) return false;
+    tx = t % gx;
+    ty = t / gx;
+    return true;
+}
+
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+__global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
+                                                  double* __restrict__ fout, const double* __restrict__ lin,
+                                                  double* __restrict__ lout, int gx, int ntiles) {
+    int tx, ty;
+    if (!tile_of(blockIdx.x, gx, ntiles, tx, ty)) return;
+    const int x = tx * TX + (int)(threadIdx.x % TX);
+    const int y = ty * TY + (int)(threadIdx.x / TX);
+    if (x >= c->nx || y >= c->ny) return;
+    step_cell<AMOD, CHEM, GEXP>(c, c->mat, x, y, fin, fout, lin, lout);
+}
+
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
+                        double* lout, hipStream_t st) {
+    const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
+    const int ntiles = gx * gy;
+    const int per = (ntiles + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
+                       fout, lin, lout, gx, ntiles);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
+                        const double* lin, double* lout, hipStream_t st) {
+    switch (flags) {
+        case 0: return launch_tiles<TX, TY, false, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 1: return launch_tiles<TX, TY, true, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 2: return launch_tiles<TX, TY, false, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 3: return launch_tiles<TX, TY, true, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 6: return launch_tiles<TX, TY, false, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
+        default: return launch_tiles<TX, TY, true, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
+    }
+}
+
+}  // namespace
+
+// Tile shapes compiled in; the index is the launch variant.
+const int kStepVariants[][2] = {{256, 2}, {256, 1}, {128, 2}, {64, 4}};
+const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
+
+int step_flags(const Consts& c) {
+    const bool chem = c.chem != 0;
+    return (c.amod ? 1 : 0) | (chem ? 2 : 0) | ((chem && !(c.m_is_one && c.n_is_one)) ? 4 : 0);
+}
+
+hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
+                       double* fout, const double* lin, double* lout, hipStream_t st) {
+    switch (variant) {
+        case 1: return launch_flags<256, 1>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 2: return launch_flags<128, 2>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 3: return launch_flags<64, 4>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        default: return launch_flags<256, 2>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+    }
+}
+
+}  // namespace lbkm

@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbkm.so")
+# LBKM_LIBRARY may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LBKM_LIBRARY", os.path.join(HERE, "liblbkm.so"))
 
 LBKM_BC_PERIODIC = 0
 LBKM_BC_OUTFLOW = 1
@@ -63,6 +64,7 @@ SIGNATURES = {
     "lbkm_set_state": [_P, _P, _P],
     "lbkm_get_step_count": [_P, ctypes.POINTER(ctypes.c_int64)],
     "lbkm_get_matrices": [_P, _D, _D, _D],
+    "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_tne_loss": [_P, _P, _P, _P],
@@ -221,6 +223,9 @@ class Sim:
         lam = _dev(lam, self.device).reshape(self.ny, self.nx).contiguous()
         self._call("lbkm_set_state", _ptr(f), _ptr(lam))
         self._keep = (f, lam)
+
+    def set_tile(self, tile_x: int, tile_y: int):
+        self._call("lbkm_set_tile", ctypes.c_int32(tile_x), ctypes.c_int32(tile_y))
 
     def step_count(self) -> int:
         v = ctypes.c_int64()
