@@ -137,10 +137,12 @@ lbkm_status lbkm_check(lbkm_ctx* ctx);
 lbkm_status lbkm_get_state(lbkm_ctx* ctx, double* f, double* lam);
 lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam);
 
-/* Work-group tile of the step kernel, tile_x x tile_y cells.  Compiled shapes: 256x2
- * (default), 256x1, 128x2, 64x4; LBKM_EINVAL for any other.  Results do not depend on
- * the tile. */
-lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y);
+/* Launch shape of the step kernel: a work-group updates a tile_x x tile_y tile; with
+ * lds != 0 it stages each plane's tile and stencil halo in LDS, else it reads the stencil
+ * through the caches.  Compiled shapes: (256,2,0) (default), (256,1,0), (64,4,0),
+ * (64,4,1), (32,8,1), (128,2,1); LBKM_EINVAL for any other.  Results do not depend on the
+ * launch shape (bitwise). */
+lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t lds);
 
 /* Host copies of the dense 24x24 moment matrix M (row k = moment m_{k+1}, column i =
  * velocity i) and of M^-1, both row-major, reassembled from the symmetry blocks the

@@ -22,7 +22,7 @@ struct lbkm_ctx {
     double* lam[2] = {nullptr, nullptr};
     int64_t pitch = 0;
     int cur = 0;
-    int step_variant = 0;              // tile shape of the step kernel (kStepVariants)
+    int step_variant = 3;              // launch shape of the step kernel (kStepVariants): 256x2 direct
     bool bound = false, params = false, fields = false;
     int64_t steps = 0;
     double cond = 0.0;

@@ -7,7 +7,7 @@
 
 namespace lbkm {
 
-extern const int kStepVariants[][2];   // {tile_x, tile_y} per launch variant (step.hip)
+extern const int kStepVariants[][3];   // {tile_x, tile_y, lds} per launch variant (step.hip)
 extern const int kNumStepVariants;
 int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,

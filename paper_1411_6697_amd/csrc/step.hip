@@ -166,6 +166,126 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     st(Lo, 0u, s.c, lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
 }
 
+// ---------------------------------------------------------------------------------------
+// LDS-staged variant.  Phase 1 is the same per-cell collision; in phase 2 the work-group
+// stages each velocity plane's tile plus a two-cell halo, (TX+4) x (TY+4) values, in LDS
+// with coalesced loads (one per value instead of the seven stencil loads per cell), and
+// every thread reads its NND stencil from there.  Plane i+1 is fetched into registers
+// while plane i is being differenced (double-buffered patch, one barrier per plane).
+template <int TX, int TY>
+struct Patch {
+    static constexpr int PW = TX + 4, PH = TY + 4, N = PW * PH;
+    static constexpr int NT = TX * TY;
+    static constexpr int NS = (N + NT - 1) / NT;     // patch values loaded per thread
+};
+
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+__device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, const Mats& M, int x0, int y0,
+                                              const double* __restrict__ fin, double* __restrict__ fout,
+                                              const double* __restrict__ lin, double* __restrict__ lout,
+                                              double* __restrict__ patch /* [2][PW*PH] */) {
+    using P = Patch<TX, TY>;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inside = x < c->nx && y < c->ny;
+    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
+    const Soa L = soa(lin, 0), Lo = soa(lout, 0);
+
+    // the patch values this thread loads: LDS index and within-plane byte offset
+    uint32_t goff[P::NS];
+#pragma unroll
+    for (int j = 0; j < P::NS; ++j) {
+        const int k = tid + j * P::NT;
+        const int px = k % P::PW, py = k / P::PW;
+        const int gx = wrap(x0 - 2 + px, c->nx, c->bc_x);
+        const int gy = wrap(y0 - 2 + py, c->ny, c->bc_y);
+        goff[j] = ((uint32_t)gy * (uint32_t)c->pitch + (uint32_t)gx) * 8u;
+    }
+
+    // Phase 1: collision and chemistry of this thread's cell
+    double src[NV], dlam = 0.0, lam = 0.0;
+    Macro m{1.0, 0.0, 0.0, 1.0};
+    if (inside) {
+        const Off s = stencil_offsets(c, x, y);
+        double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
+        if (AMOD) {
+            double nb[NV], ua, va, ub, vb;
+            load_cell(F, s.xp1, nb);
+            velocity_of(c, nb, ua, va);
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.xm1, nb);
+            velocity_of(c, nb, ub, vb);
+            gxx = (ua - ub) * c->half_inv_dx;
+            gyx = (va - vb) * c->half_inv_dx;
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.yp1, nb);
+            velocity_of(c, nb, ua, va);
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, s.ym1, nb);
+            velocity_of(c, nb, ub, vb);
+            gxy = (ua - ub) * c->half_inv_dy;
+            gyy = (va - vb) * c->half_inv_dy;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double f[NV];
+        load_cell(F, s.c, f);
+        Blocks sb, h;
+        to_combos(f, sb);
+        forward(M, sb, h);
+        m = macro_of(h, c->DI);
+        double A8 = 0.0, A9 = 0.0;
+        if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
+        lam = ld(L, 0u, s.c);
+        local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) src[i] = 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // Phase 2: planes 0..23 of f, then lambda (plane 24), through the LDS patch
+    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+    const uint32_t pb = opaque(F.plane_bytes);
+    const uint32_t out_off = ((uint32_t)y * (uint32_t)c->pitch + (uint32_t)x) * 8u;
+    const int cidx = (ly + 2) * P::PW + (lx + 2);
+    double pre[P::NS];
+    auto fetch = [&](int plane) {
+#pragma unroll
+        for (int j = 0; j < P::NS; ++j) {
+            if (P::N % P::NT == 0 || tid + j * P::NT < P::N)
+                pre[j] = (plane < NV) ? ld(F, (uint32_t)plane * pb, goff[j]) : ld(L, 0u, goff[j]);
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        double* buf = patch + (i & 1) * P::N;
+#pragma unroll
+        for (int j = 0; j < P::NS; ++j)
+            if (P::N % P::NT == 0 || tid + j * P::NT < P::N) buf[tid + j * P::NT] = pre[j];
+        __syncthreads();
+        if (i < NV) fetch(i + 1);
+        const double* q = buf + cidx;
+        const double f0 = q[0];
+        if (i < NV) {
+            const int g = i / 8, d = i % 8;
+            const double v = c->vg[g];
+            double adv = 0.0;
+            if (DUX[d] > 0) adv += v * (nnd_pos(q[-2], q[-1], f0, q[1]) * idx_);
+            if (DUX[d] < 0) adv -= v * (nnd_neg(q[-1], f0, q[1], q[2]) * idx_);
+            if (DUY[d] > 0) adv += v * (nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]) * idy);
+            if (DUY[d] < 0) adv -= v * (nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]) * idy);
+            if (inside) st(G, (uint32_t)i * pb, out_off, f0 + dt * (src[i] - adv));
+        } else if (inside) {
+            const double dlx = (m.ux > 0.0) ? nnd_pos(q[-2], q[-1], f0, q[1]) : nnd_neg(q[-1], f0, q[1], q[2]);
+            const double dly = (m.uy > 0.0) ? nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW])
+                                            : nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
+            st(Lo, 0u, out_off, f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+        }
+    }
+}
+
 // tile t of the XCD-aware order for work-group b; returns false past the last tile
 __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int& tx, int& ty) {
     const int per = (ntiles + kXcds - 1) / kXcds;
@@ -189,33 +309,49 @@ __global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c, 
 }
 
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+__global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__ c,
+                                                      const double* __restrict__ fin, double* __restrict__ fout,
+                                                      const double* __restrict__ lin, double* __restrict__ lout,
+                                                      int gx, int ntiles) {
+    __shared__ double patch[2 * Patch<TX, TY>::N];
+    int tx, ty;
+    if (!tile_of(blockIdx.x, gx, ntiles, tx, ty)) return;
+    step_tile_lds<TX, TY, AMOD, CHEM, GEXP>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, patch);
+}
+
+template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
                         double* lout, hipStream_t st) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
-                       fout, lin, lout, gx, ntiles);
+    if (LDS)
+        hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
+                           fin, fout, lin, lout, gx, ntiles);
+    else
+        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
+                           fout, lin, lout, gx, ntiles);
     return hipGetLastError();
 }
 
-template <int TX, int TY>
+template <int TX, int TY, bool LDS>
 hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
                         const double* lin, double* lout, hipStream_t st) {
     switch (flags) {
-        case 0: return launch_tiles<TX, TY, false, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 1: return launch_tiles<TX, TY, true, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 2: return launch_tiles<TX, TY, false, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 3: return launch_tiles<TX, TY, true, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 6: return launch_tiles<TX, TY, false, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
-        default: return launch_tiles<TX, TY, true, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
+        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
     }
 }
 
 }  // namespace
 
-// Tile shapes compiled in; the index is the launch variant.
-const int kStepVariants[][2] = {{256, 2}, {256, 1}, {128, 2}, {64, 4}};
+// Launch variants compiled in: {tile_x, tile_y, lds}.  lds = 1 stages the stencil planes
+// in LDS; lds = 0 reads the stencil straight from the caches.
+const int kStepVariants[][3] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}, {256, 2, 0}, {256, 1, 0}, {64, 4, 0}};
 const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 
 int step_flags(const Consts& c) {
@@ -226,10 +362,12 @@ int step_flags(const Consts& c) {
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, hipStream_t st) {
     switch (variant) {
-        case 1: return launch_flags<256, 1>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 2: return launch_flags<128, 2>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 3: return launch_flags<64, 4>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        default: return launch_flags<256, 2>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
     }
 }
 

@@ -64,7 +64,7 @@ SIGNATURES = {
     "lbkm_set_state": [_P, _P, _P],
     "lbkm_get_step_count": [_P, ctypes.POINTER(ctypes.c_int64)],
     "lbkm_get_matrices": [_P, _D, _D, _D],
-    "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32],
+    "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_tne_loss": [_P, _P, _P, _P],
@@ -224,8 +224,8 @@ class Sim:
         self._call("lbkm_set_state", _ptr(f), _ptr(lam))
         self._keep = (f, lam)
 
-    def set_tile(self, tile_x: int, tile_y: int):
-        self._call("lbkm_set_tile", ctypes.c_int32(tile_x), ctypes.c_int32(tile_y))
+    def set_tile(self, tile_x: int, tile_y: int, lds: int = 1):
+        self._call("lbkm_set_tile", ctypes.c_int32(tile_x), ctypes.c_int32(tile_y), ctypes.c_int32(lds))
 
     def step_count(self) -> int:
         v = ctypes.c_int64()
