@@ -184,33 +184,44 @@ const char* lbkm_last_error(const lbkm_ctx* ctx);
 lbkm_status lbkm_destroy(lbkm_ctx* ctx);
 
 /* ---- batched 1D instances ------------------------------------------------ */
-/* Many independent 1D runs (Ny = 1, outflow at both ends) of ragged lengths
- * nx[k], sharing dx, dt, the velocity model, gamma, Q and the rate law, each with
- * its own R_1..R_24.  The library owns the packed state (f[24][total] and
- * lambda[total], instances laid out back to back).  One lbkm_batch_step call
- * replays a captured HIP graph that advances every instance n steps with one
- * persistent kernel launch per chunk of steps. */
+/* Many independent 1D runs of ragged lengths nx[k] (Ny = 1, zero-gradient outflow at
+ * both ends, as the 1D problems of Sec. IV), sharing dx, dt, the velocity model
+ * (Sec. III), gamma, Q and the rate law (Eq. for F, Sec. II), each with its own
+ * R_1..R_24 (and Prandtl number).  The library owns the packed state: f[24][P] and
+ * lambda[P], P = sum(nx) rounded up to 64, instances back to back.  One
+ * lbkm_batch_step call replays a captured HIP graph holding one persistent kernel
+ * launch that advances every instance n steps; neighbouring work-groups synchronise
+ * through per-work-group step counters, every wait is bounded, and a wait that runs
+ * out (work-groups not co-resident) sets a sticky error that lbkm_batch_status reports.
+ * Calls on one context are ordered on its stream; two contexts may run concurrently.
+ * Errors: LBKM_EINVAL for bad sizes or rates (checked per instance, message names it),
+ * LBKM_ESTATE for calls out of order, LBKM_EDEVICE for HIP failures. */
 
-/* common->nx, ny, bc_x, bc_y are ignored (each instance is nx[k] x 1, outflow). */
+/* n_inst >= 1 instances, nx: host [n_inst], every nx[k] >= 1, sum(nx) < 2^28 and the
+ * state within 4 GiB.  common supplies dx, dy, dt and the velocity model; its nx, ny,
+ * bc_x and bc_y are ignored.  Allocates the state on the current device. */
 lbkm_status lbkm_batch_create(int32_t n_inst, const int32_t* nx, const lbkm_grid* common,
                               void* hip_stream, lbkm_ctx** out);
 
 /* S: host [n_inst][24] rates; Pr: host [n_inst] or NULL (same meaning as in
- * lbkm_set_params, per instance); gamma, Q and rates shared. */
+ * lbkm_set_params, per instance); gamma, Q and rates shared.  Synchronous. */
 lbkm_status lbkm_batch_set_params(lbkm_ctx* ctx, const double* S, const double* Pr,
                                   double gamma, double Q, const lbkm_rates* rates);
 
 /* Initial fields, packed back to back: rho, ux, uy, T, lambda of sum(nx) doubles
- * each (device pointers). */
+ * each (device pointers, read on the stream).  Clears the step count and the error. */
 lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
                                    const double* uy, const double* T, const double* lambda);
 
-/* Choose the tile (cells per work-group) by timing candidates on this device
- * (autotuner; the state is saved and restored around the trial runs).  If never
- * called, a default tile is used.  *tile_out (host, may be NULL) receives the choice. */
-lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* tile_out);
+/* Autotuner: times a few steps for each candidate number of work-groups per compute
+ * unit (within the occupancy the device reports) and keeps the fastest.  The state
+ * and the step count are saved and restored around the trials.  If never called,
+ * two work-groups per compute unit are used.  *cells_per_wg (host, may be NULL)
+ * receives the resulting cells per work-group.  Synchronous. */
+lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg);
 
-/* Advance every instance n steps (asynchronous; replays a captured graph). */
+/* Advance every instance n steps, 0 <= n < 2^31 (asynchronous; replays a captured
+ * graph, one per buffer parity and n). */
 lbkm_status lbkm_batch_step(lbkm_ctx* ctx, int64_t n);
 
 /* Packed macroscopic readout (sum(nx) doubles each, device, NULL allowed). */
@@ -219,6 +230,11 @@ lbkm_status lbkm_batch_get_moments(lbkm_ctx* ctx, double* rho, double* ux, doubl
 
 /* Total number of cells sum(nx) (host). */
 lbkm_status lbkm_batch_total_cells(lbkm_ctx* ctx, int64_t* out);
+
+/* Synchronises the stream; LBKM_EDEVICE if a neighbour wait of any launch since the
+ * last init ran out (the results are then invalid).  wgs, wgs_per_cu (host, may be
+ * NULL) receive the current launch shape. */
+lbkm_status lbkm_batch_status(lbkm_ctx* ctx, int32_t* wgs, int32_t* wgs_per_cu);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,552 @@
+// Batched 1D instances: many independent detonation tubes of uneven length advanced by
+// one persistent kernel launch (replayed from a captured HIP graph).
+//
+// Layout: the instances' cells are packed back to back (global cell index j), state f[24][P]
+// and lambda[P] with P = total cells rounded up to 64; each buffer exists twice (ping-pong).
+// Every instance is nx x 1, y-periodic, with zero-gradient outflow at both x ends, so the
+// y-differences of the NND scheme and of A_hat vanish identically and are not evaluated.
+//
+// Work decomposition: the packed cells are cut into `nwg` contiguous ranges of nearly
+// equal size, one per work-group, with all work-groups resident at once (their number is
+// bounded by the occupancy the device reports).  A range is split into segments at
+// instance boundaries, so each segment's rates are wave-uniform (scalar loads).  For each
+// step a work-group updates its range from buffer `cur` into the other buffer; it may start
+// step s+1 once both neighbouring ranges have completed step s (then their step-s values,
+// its halo, are final, and they no longer read the buffer it is about to overwrite).  The
+// counters are published with device-scope release after a device-scope fence and read
+// with acquire, which invalidates the reader's L1.  Waiting is bounded: past the spin
+// limit the kernel records an error and every work-group returns, so the launch always
+// drains.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lbkm_abi_internal.h"
+#include "lbkm_device.h"
+#include "lbkm_kernels.h"
+
+namespace lbkm {
+
+struct BatchInst {
+    double R[NV];
+    double a8c, a9c;
+    int32_t amod, pad;
+};
+
+struct BatchSeg {
+    int32_t inst;        // instance index
+    int32_t begin, end;  // global cells [begin, end) updated by this segment
+    int32_t lo, hi;      // first and last global cell of the instance (outflow clamp)
+};
+
+constexpr int kBatchThreads = 256;
+constexpr int kSpinLimit = 1 << 20;   // neighbour waits are bounded (error, never a hang)
+
+struct BatchState {
+    int32_t n_inst = 0;
+    std::vector<int32_t> nx;
+    std::vector<int32_t> off;
+    int64_t total = 0, plane = 0;
+    double* f[2] = {nullptr, nullptr};
+    double* lam[2] = {nullptr, nullptr};
+    int cur = 0;
+    std::vector<BatchInst> h_inst;
+    BatchInst* d_inst = nullptr;
+    bool any_amod = false;
+    // launch decomposition
+    int wgs_per_cu = 2, nwg = 0, cus = 0;
+    BatchSeg* d_seg = nullptr;
+    int32_t* d_wg_seg = nullptr;
+    int seg_cap = 0;
+    uint32_t* d_flags = nullptr;
+    int32_t* d_err = nullptr;
+    // captured graphs: [parity]
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int64_t exec_steps[2] = {-1, -1};
+    int exec_nwg[2] = {-1, -1};
+    hipStream_t cap = nullptr;
+};
+
+namespace {
+
+__device__ __forceinline__ bool wait_counter(const uint32_t* flags, int nb, int nwg, uint32_t want,
+                                             const int32_t* err) {
+    if (nb < 0 || nb >= nwg) return true;
+    for (int k = 0; k < kSpinLimit; ++k) {
+        if (__hip_atomic_load(flags + nb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
+// one step of one cell of a 1D instance (x-derivatives only; y-differences are zero)
+template <bool AMOD, bool CHEM, bool GEXP>
+__device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const BatchInst* __restrict__ I, int lo,
+                                        int hi, int j, const Soa& F, const Soa& G, const Soa& L, const Soa& Lo) {
+    const uint32_t oc = (uint32_t)j * 8u;
+    const uint32_t om2 = (uint32_t)max(j - 2, lo) * 8u, om1 = (uint32_t)max(j - 1, lo) * 8u;
+    const uint32_t op1 = (uint32_t)min(j + 1, hi) * 8u, op2 = (uint32_t)min(j + 2, hi) * 8u;
+
+    double src[NV], dlam, lam;
+    Macro m;
+    {
+        double gxx = 0.0, gyx = 0.0;
+        if (AMOD && I->amod) {
+            double nb[NV], ua, va, ub, vb;
+            load_cell(F, op1, nb);
+            velocity_of(c, nb, ua, va);
+            __builtin_amdgcn_sched_barrier(0);
+            load_cell(F, om1, nb);
+            velocity_of(c, nb, ub, vb);
+            gxx = (ua - ub) * c->half_inv_dx;
+            gyx = (va - vb) * c->half_inv_dx;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double f[NV];
+        load_cell(F, oc, f);
+        Blocks sb, h;
+        to_combos(f, sb);
+        forward(c->mat, sb, h);
+        m = macro_of(h, c->DI);
+        double A8 = 0.0, A9 = 0.0;
+        if (AMOD && I->amod) modification(I->a8c, I->a9c, c->DI, m, gxx, 0.0, gyx, 0.0, A8, A9);
+        lam = ld(L, 0u, oc);
+        local_source<CHEM, GEXP>(c, c->mat, lam, A8, A9, m, h, src, dlam, I->R);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const double dt = c->dt, idx_ = c->inv_dx;
+    const uint32_t pb = opaque(F.plane_bytes);
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double v = c->vg[g];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const uint32_t so = (uint32_t)(8 * g + d) * pb;
+            const double f0 = ld(F, so, oc);
+            double adv = 0.0;
+            if (DUX[d] > 0) adv += v * (nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)) * idx_);
+            if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)) * idx_);
+            st(G, so, oc, f0 + dt * (src[8 * g + d] - adv));
+        }
+    }
+    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, om2), ld(L, 0u, om1), lam, ld(L, 0u, op1))
+                                    : nnd_neg(ld(L, 0u, om1), lam, ld(L, 0u, op1), ld(L, 0u, op2));
+    st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
+}
+
+template <bool AMOD, bool CHEM, bool GEXP>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restrict__ c,
+                                                         const BatchInst* __restrict__ inst,
+                                                         const BatchSeg* __restrict__ segs,
+                                                         const int32_t* __restrict__ wg_seg, int nwg,
+                                                         double* f0, double* f1, double* l0, double* l1,
+                                                         int64_t steps, int parity, uint32_t* flags,
+                                                         int32_t* err) {
+    const int w = blockIdx.x;
+    const int sbeg = wg_seg[w], send = wg_seg[w + 1];
+    __shared__ int32_t stop;
+    // the descriptors are swapped after every step (selecting them by step parity inside
+    // the loop would turn them into per-lane values)
+    Soa F = soa(parity ? f1 : f0, c->plane), G = soa(parity ? f0 : f1, c->plane);
+    Soa L = soa(parity ? l1 : l0, 0), Lo = soa(parity ? l0 : l1, 0);
+    for (int64_t s = 0; s < steps; ++s) {
+        if (s > 0) {
+            if (threadIdx.x == 0) {
+                const uint32_t want = (uint32_t)s;
+                const bool ok = wait_counter(flags, w - 1, nwg, want, err) &&
+                                wait_counter(flags, w + 1, nwg, want, err);
+                if (!ok) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                stop = ok ? 0 : 1;
+            }
+            __syncthreads();
+            if (__builtin_amdgcn_readfirstlane(stop)) return;   // uniform over the work-group
+        }
+        for (int q = sbeg; q < send; ++q) {
+            const BatchSeg S = segs[q];
+            const BatchInst* I = inst + S.inst;
+            // uniform trip count; the tail is masked
+            for (int base = S.begin; base < S.end; base += kBatchThreads) {
+                const int j = base + (int)threadIdx.x;
+                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, j, F, G, L, Lo);
+            }
+        }
+        __threadfence();               // this thread's stores are visible device-wide
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(flags + w, (uint32_t)(s + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        Soa t = F;
+        F = G;
+        G = t;
+        t = L;
+        L = Lo;
+        Lo = t;
+    }
+}
+
+// clears the step counters before each persistent launch (a kernel, so that the clear can
+// sit in a captured graph)
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+template <bool AMOD, bool CHEM, bool GEXP>
+void launch_batch_kernel(const Consts* dc, BatchState* b, int64_t steps, int parity, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch<AMOD, CHEM, GEXP>), dim3(b->nwg), dim3(kBatchThreads), 0, st, dc, b->d_inst,
+                       b->d_seg, b->d_wg_seg, b->nwg, b->f[0], b->f[1], b->lam[0], b->lam[1], steps, parity,
+                       b->d_flags, b->d_err);
+}
+
+const void* batch_kernel_ptr(int flags) {
+    switch (flags) {
+        case 0: return (const void*)k_batch<false, false, false>;
+        case 1: return (const void*)k_batch<true, false, false>;
+        case 2: return (const void*)k_batch<false, true, false>;
+        case 3: return (const void*)k_batch<true, true, false>;
+        case 6: return (const void*)k_batch<false, true, true>;
+        default: return (const void*)k_batch<true, true, true>;
+    }
+}
+
+hipError_t launch_batch(const Consts* dc, int flags, BatchState* b, int64_t steps, int parity, hipStream_t st) {
+    const int nflags = b->nwg + 2;
+    hipLaunchKernelGGL(k_zero_u32, dim3((nflags + 255) / 256), dim3(256), 0, st, b->d_flags, nflags);
+    switch (flags) {
+        case 0: launch_batch_kernel<false, false, false>(dc, b, steps, parity, st); break;
+        case 1: launch_batch_kernel<true, false, false>(dc, b, steps, parity, st); break;
+        case 2: launch_batch_kernel<false, true, false>(dc, b, steps, parity, st); break;
+        case 3: launch_batch_kernel<true, true, false>(dc, b, steps, parity, st); break;
+        case 6: launch_batch_kernel<false, true, true>(dc, b, steps, parity, st); break;
+        default: launch_batch_kernel<true, true, true>(dc, b, steps, parity, st); break;
+    }
+    return hipGetLastError();
+}
+
+int batch_flags(const Consts& c, const BatchState* b) {
+    const bool chem = c.chem != 0;
+    return (b->any_amod ? 1 : 0) | (chem ? 2 : 0) | ((chem && !(c.m_is_one && c.n_is_one)) ? 4 : 0);
+}
+
+void drop_graphs(BatchState* b) {
+    for (int p = 0; p < 2; ++p) {
+        if (b->exec[p]) (void)hipGraphExecDestroy(b->exec[p]);
+        b->exec[p] = nullptr;
+        b->exec_steps[p] = -1;
+        b->exec_nwg[p] = -1;
+    }
+}
+
+// Cut the packed cells into nwg ranges and the ranges into per-instance segments.
+lbkm_status build_decomposition(lbkm_ctx* ctx, int wgs_per_cu) {
+    BatchState* b = ctx->batch;
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel_ptr(batch_flags(ctx->h, b)),
+                                                                 kBatchThreads, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "occupancy query");
+    if (occ < 1) return fail(ctx, LBKM_EDEVICE, "batch kernel cannot be resident");
+    const int per_cu = std::min(wgs_per_cu, occ);
+    int nwg = std::max(1, b->cus * per_cu);
+    nwg = (int)std::min<int64_t>(nwg, std::max<int64_t>(1, b->total / 64));
+    std::vector<BatchSeg> segs;
+    std::vector<int32_t> wg_seg(nwg + 1, 0);
+    int k = 0;
+    for (int w = 0; w < nwg; ++w) {
+        const int64_t a = b->total * w / nwg, z = b->total * (w + 1) / nwg;
+        wg_seg[w] = (int32_t)segs.size();
+        int64_t j = a;
+        while (j < z) {
+            while (k + 1 < b->n_inst && j >= b->off[k + 1]) ++k;
+            const int64_t lo = b->off[k], hi = b->off[k] + b->nx[k] - 1;
+            const int64_t end = std::min<int64_t>(z, hi + 1);
+            segs.push_back(BatchSeg{k, (int32_t)j, (int32_t)end, (int32_t)lo, (int32_t)hi});
+            j = end;
+        }
+    }
+    wg_seg[nwg] = (int32_t)segs.size();
+    if ((int)segs.size() > b->seg_cap || nwg + 2 > b->seg_cap) {
+        if (b->d_seg) (void)hipFree(b->d_seg);
+        if (b->d_wg_seg) (void)hipFree(b->d_wg_seg);
+        if (b->d_flags) (void)hipFree(b->d_flags);
+        b->d_seg = nullptr;
+        b->d_wg_seg = nullptr;
+        b->d_flags = nullptr;
+        b->seg_cap = std::max((int)segs.size(), nwg + 2) * 2;
+        e = hipMalloc((void**)&b->d_seg, sizeof(BatchSeg) * b->seg_cap);
+        if (e == hipSuccess) e = hipMalloc((void**)&b->d_wg_seg, sizeof(int32_t) * (b->seg_cap + 1));
+        if (e == hipSuccess) e = hipMalloc((void**)&b->d_flags, sizeof(uint32_t) * (b->seg_cap + 2));
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch decomposition allocation");
+    }
+    e = hipMemcpy(b->d_seg, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_wg_seg, wg_seg.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch decomposition upload");
+    b->nwg = nwg;
+    b->wgs_per_cu = per_cu;
+    drop_graphs(b);
+    return LBKM_OK;
+}
+
+lbkm_status batch_ready(lbkm_ctx* ctx, bool need_fields) {
+    if (!ctx) return LBKM_EINVAL;
+    if (!ctx->batched || !ctx->batch) return fail(ctx, LBKM_ESTATE, "not a batched context");
+    if (!ctx->params) return fail(ctx, LBKM_ESTATE, "parameters not set");
+    if (need_fields && !ctx->fields) return fail(ctx, LBKM_ESTATE, "fields not initialised");
+    return LBKM_OK;
+}
+
+// run `n` steps through the graph cache (one graph per buffer parity and step count)
+lbkm_status batch_run(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
+    BatchState* b = ctx->batch;
+    if (n == 0) return LBKM_OK;
+    const int p = b->cur;
+    hipError_t e = hipSuccess;
+    if (!b->exec[p] || b->exec_steps[p] != n || b->exec_nwg[p] != b->nwg) {
+        if (b->exec[p]) (void)hipGraphExecDestroy(b->exec[p]);
+        b->exec[p] = nullptr;
+        if (!b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        hipGraph_t g = nullptr;
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_batch(ctx->d, batch_flags(ctx->h, b), b, n, p, b->cap);
+            e = hipStreamEndCapture(b->cap, &g);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[p], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch graph capture");
+        b->exec_steps[p] = n;
+        b->exec_nwg[p] = b->nwg;
+    }
+    e = hipGraphLaunch(b->exec[p], st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch graph launch");
+    b->cur = (int)((p + n) & 1);
+    ctx->steps += n;
+    return LBKM_OK;
+}
+
+}  // namespace
+
+void destroy_extras(lbkm_ctx* ctx) {
+    BatchState* b = ctx->batch;
+    if (!b) return;
+    drop_graphs(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int i = 0; i < 2; ++i) {
+        if (b->f[i]) (void)hipFree(b->f[i]);
+        if (b->lam[i]) (void)hipFree(b->lam[i]);
+    }
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_seg) (void)hipFree(b->d_seg);
+    if (b->d_wg_seg) (void)hipFree(b->d_wg_seg);
+    if (b->d_flags) (void)hipFree(b->d_flags);
+    if (b->d_err) (void)hipFree(b->d_err);
+    delete b;
+    ctx->batch = nullptr;
+}
+
+}  // namespace lbkm
+
+using namespace lbkm;
+
+extern "C" {
+
+lbkm_status lbkm_batch_create(int32_t n_inst, const int32_t* nx, const lbkm_grid* common, void* hip_stream,
+                              lbkm_ctx** out) {
+    if (!out) return LBKM_EINVAL;
+    *out = nullptr;
+    if (n_inst < 1 || !nx || !common) return LBKM_EINVAL;
+    lbkm_ctx* ctx = new (std::nothrow) lbkm_ctx();
+    if (!ctx) return LBKM_ENOMEM;
+    *out = ctx;
+    ctx->batched = 1;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->grid = *common;
+    BatchState* b = new (std::nothrow) BatchState();
+    if (!b) return fail(ctx, LBKM_ENOMEM, "host allocation");
+    ctx->batch = b;
+    b->n_inst = n_inst;
+    b->nx.assign(nx, nx + n_inst);
+    b->off.resize(n_inst);
+    int64_t total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        if (nx[k] < 1) return fail(ctx, LBKM_EINVAL, "every instance needs nx >= 1");
+        b->off[k] = (int32_t)total;
+        total += nx[k];
+        if (total >= (int64_t)1 << 28) return fail(ctx, LBKM_EINVAL, "too many cells in the batch (>= 2^28)");
+    }
+    b->total = total;
+    b->plane = (total + 63) / 64 * 64;
+    lbkm_grid g = *common;
+    g.nx = (int32_t)total;
+    g.ny = 1;
+    g.bc_x = LBKM_BC_OUTFLOW;
+    g.bc_y = LBKM_BC_PERIODIC;
+    ctx->grid = g;
+    lbkm_status st = validate_grid_common(ctx, &g);
+    if (st == LBKM_OK) st = build_tables(ctx, &g);
+    if (st != LBKM_OK) return st;
+    ctx->h.pitch = b->plane;
+    ctx->h.plane = b->plane;
+    st = ensure_device_tables(ctx);
+    if (st != LBKM_OK) return st;
+    if ((int64_t)NV * b->plane * 8 > 0xFFFFFFFFll) return fail(ctx, LBKM_EINVAL, "batch state exceeds 4 GiB");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipMalloc((void**)&b->f[i], sizeof(double) * NV * b->plane);
+        if (e == hipSuccess) e = hipMalloc((void**)&b->lam[i], sizeof(double) * b->plane);
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_inst, sizeof(BatchInst) * n_inst);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_err, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch allocation");
+    b->h_inst.resize(n_inst);
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_batch_set_params(lbkm_ctx* ctx, const double* S, const double* Pr, double gamma, double Q,
+                                  const lbkm_rates* rates) {
+    if (!ctx) return LBKM_EINVAL;
+    if (!ctx->batched || !ctx->batch) return fail(ctx, LBKM_ESTATE, "not a batched context");
+    if (!S) return fail(ctx, LBKM_EINVAL, "NULL rates");
+    BatchState* b = ctx->batch;
+    Consts trial = ctx->h;
+    bool any_amod = false;
+    for (int k = 0; k < b->n_inst; ++k) {
+        Consts ck = ctx->h;
+        lbkm_status st = fill_physics(ctx, &ck, S + 24 * k, gamma, Pr ? Pr[k] : 0.0, Q, rates, ctx->grid.dt);
+        if (st != LBKM_OK) return fail(ctx, st, "instance " + std::to_string(k) + ": " + ctx->err);
+        if (k == 0) trial = ck;
+        BatchInst& I = b->h_inst[k];
+        std::memcpy(I.R, ck.R, sizeof(I.R));
+        I.a8c = ck.a8c;
+        I.a9c = ck.a9c;
+        I.amod = ck.amod;
+        any_amod |= ck.amod != 0;
+    }
+    ctx->h = trial;
+    b->any_amod = any_amod;
+    hipError_t e = hipMemcpy(b->d_inst, b->h_inst.data(), sizeof(BatchInst) * b->n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch parameter upload");
+    ctx->params = true;
+    lbkm_status st = upload_consts(ctx);
+    if (st != LBKM_OK) return st;
+    return build_decomposition(ctx, b->wgs_per_cu);
+}
+
+lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                                   const double* T, const double* lambda) {
+    lbkm_status st = batch_ready(ctx, false);
+    if (st != LBKM_OK) return st;
+    if (!rho || !ux || !uy || !T || !lambda) return fail(ctx, LBKM_EINVAL, "NULL field");
+    BatchState* b = ctx->batch;
+    b->cur = 0;
+    hipError_t e = hipMemsetAsync(b->d_err, 0, sizeof(int32_t), ctx->stream);   // a new run clears the error
+    if (e == hipSuccess) e = launch_init(ctx->d, (int)b->total, 1, rho, ux, uy, T, lambda, b->f[0], b->lam[0], ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch init kernel");
+    ctx->fields = true;
+    ctx->steps = 0;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_batch_step(lbkm_ctx* ctx, int64_t n) {
+    lbkm_status st = batch_ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    if (n < 0 || n > 0x7FFFFFFF) return fail(ctx, LBKM_EINVAL, "n out of range");
+    return batch_run(ctx, n, ctx->stream);
+}
+
+lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg) {
+    lbkm_status st = batch_ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    BatchState* b = ctx->batch;
+    // save the state, time a few steps per candidate, restore
+    double *sf = nullptr, *sl = nullptr;
+    hipError_t e = hipMalloc((void**)&sf, sizeof(double) * NV * b->plane);
+    if (e == hipSuccess) e = hipMalloc((void**)&sl, sizeof(double) * b->plane);
+    const int cur = b->cur;
+    const int64_t steps0 = ctx->steps;
+    if (e == hipSuccess) e = hipMemcpyAsync(sf, b->f[cur], sizeof(double) * NV * b->plane, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sl, b->lam[cur], sizeof(double) * b->plane, hipMemcpyDeviceToDevice, ctx->stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    int best = b->wgs_per_cu;
+    float best_ms = 1e30f;
+    const int cands[] = {1, 2, 3, 4, 6, 8};
+    for (int cand : cands) {
+        if (e != hipSuccess) break;
+        st = build_decomposition(ctx, cand);
+        if (st != LBKM_OK) break;
+        if (b->wgs_per_cu != cand) continue;                 // occupancy does not allow it
+        const int64_t trial = 16;
+        e = hipMemsetAsync(b->d_err, 0, sizeof(int32_t), ctx->stream);
+        if (e != hipSuccess) break;
+        st = batch_run(ctx, 2, ctx->stream);                  // warm-up (also captures)
+        if (st == LBKM_OK) st = batch_run(ctx, trial, ctx->stream);   // capture the timed graph
+        if (st != LBKM_OK) break;
+        e = hipEventRecord(t0, ctx->stream);
+        if (e == hipSuccess) st = batch_run(ctx, trial, ctx->stream);
+        if (e == hipSuccess && st == LBKM_OK) e = hipEventRecord(t1, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        int32_t err = 0;
+        if (e == hipSuccess) e = hipMemcpy(&err, b->d_err, sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && err == 0 && ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    if (e == hipSuccess && st == LBKM_OK) st = build_decomposition(ctx, best);
+    b->cur = cur;
+    ctx->steps = steps0;
+    if (e == hipSuccess) e = hipMemcpyAsync(b->f[cur], sf, sizeof(double) * NV * b->plane, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->lam[cur], sl, sizeof(double) * b->plane, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_err, 0, sizeof(int32_t), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (sf) (void)hipFree(sf);
+    if (sl) (void)hipFree(sl);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch autotune");
+    if (st != LBKM_OK) return st;
+    if (cells_per_wg) *cells_per_wg = (int32_t)((b->total + b->nwg - 1) / b->nwg);
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_batch_get_moments(lbkm_ctx* ctx, double* rho, double* ux, double* uy, double* T, double* p,
+                                   double* lambda) {
+    lbkm_status st = batch_ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    BatchState* b = ctx->batch;
+    hipError_t e = launch_moments(ctx->d, (int)b->total, 1, b->f[b->cur], b->lam[b->cur], rho, ux, uy, T, p,
+                                  lambda, ctx->stream);
+    return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "batch moments kernel");
+}
+
+lbkm_status lbkm_batch_total_cells(lbkm_ctx* ctx, int64_t* out) {
+    if (!ctx || !out) return LBKM_EINVAL;
+    if (!ctx->batched || !ctx->batch) return fail(ctx, LBKM_ESTATE, "not a batched context");
+    *out = ctx->batch->total;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_batch_status(lbkm_ctx* ctx, int32_t* wgs, int32_t* wgs_per_cu) {
+    if (!ctx) return LBKM_EINVAL;
+    if (!ctx->batched || !ctx->batch) return fail(ctx, LBKM_ESTATE, "not a batched context");
+    int32_t err = 0;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(&err, ctx->batch->d_err, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch status");
+    if (wgs) *wgs = ctx->batch->nwg;
+    if (wgs_per_cu) *wgs_per_cu = ctx->batch->wgs_per_cu;
+    if (err) return fail(ctx, LBKM_EDEVICE, "a neighbour wait exceeded its bound (work-groups not co-resident)");
+    return LBKM_OK;
+}
+
+}  // extern "C"

@@ -252,20 +252,22 @@ __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double l
 template <bool CHEM = true, bool GEXP = true>
 __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const Mats& M, double lam,
                                              double A8, double A9, const Macro& m, const Blocks& h,
-                                             double src[NV], double& dlam) {
+                                             double src[NV], double& dlam,
+                                             const double* __restrict__ Rk = nullptr) {
+    const double* __restrict__ R = Rk ? Rk : c->R;     // R_1..R_24 (per instance when batched)
     {
         Blocks e;
         equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
         // g = R (f_hat - f_hat^eq) - A_hat, Delta_1..4 = 0
         Blocks g;
 #pragma unroll
-        for (int r = 0; r < NEE; ++r) g.ee[r] = c->R[EE_M[r]] * (h.ee[r] - e.ee[r]);
+        for (int r = 0; r < NEE; ++r) g.ee[r] = R[EE_M[r]] * (h.ee[r] - e.ee[r]);
 #pragma unroll
-        for (int r = 0; r < NOE; ++r) g.oe[r] = c->R[OE_M[r]] * (h.oe[r] - e.oe[r]);
+        for (int r = 0; r < NOE; ++r) g.oe[r] = R[OE_M[r]] * (h.oe[r] - e.oe[r]);
 #pragma unroll
-        for (int r = 0; r < NEO; ++r) g.eo[r] = c->R[EO_M[r]] * (h.eo[r] - e.eo[r]);
+        for (int r = 0; r < NEO; ++r) g.eo[r] = R[EO_M[r]] * (h.eo[r] - e.eo[r]);
 #pragma unroll
-        for (int r = 0; r < NOO; ++r) g.oo[r] = c->R[OO_M[r]] * (h.oo[r] - e.oo[r]);
+        for (int r = 0; r < NOO; ++r) g.oo[r] = R[OO_M[r]] * (h.oo[r] - e.oo[r]);
         g.ee[0] = 0.0;   // m1
         g.ee[1] = 0.0;   // m4
         g.oe[0] = 0.0;   // m2
@@ -309,15 +311,62 @@ __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const
 }
 
 // A_hat_8, A_hat_9 (Eqs. ArtificialA8/ArtificialA9) from central differences of u
-__device__ __forceinline__ void modification(const Consts* __restrict__ c, const Macro& m,
+__device__ __forceinline__ void modification(double a8c, double a9c, double DI, const Macro& m,
                                              double dux_dx, double dux_dy, double duy_dx,
                                              double duy_dy, double& A8, double& A9) {
     const double rT = m.rho * m.T;
-    const double iDI = 1.0 / c->DI;
-    A8 = rT * c->a8c * (4.0 * m.ux * (dux_dx - dux_dx * iDI - duy_dy * iDI) +
-                        2.0 * m.uy * (duy_dx + dux_dy));
-    A9 = rT * c->a9c * (4.0 * m.uy * (duy_dy - dux_dx * iDI - duy_dy * iDI) +
-                        2.0 * m.ux * (duy_dx + dux_dy));
+    const double iDI = 1.0 / DI;
+    A8 = rT * a8c * (4.0 * m.ux * (dux_dx - dux_dx * iDI - duy_dy * iDI) +
+                     2.0 * m.uy * (duy_dx + dux_dy));
+    A9 = rT * a9c * (4.0 * m.uy * (duy_dy - dux_dx * iDI - duy_dy * iDI) +
+                     2.0 * m.ux * (duy_dx + dux_dy));
+}
+__device__ __forceinline__ void modification(const Consts* __restrict__ c, const Macro& m,
+                                             double dux_dx, double dux_dy, double duy_dx,
+                                             double duy_dy, double& A8, double& A9) {
+    modification(c->a8c, c->a9c, c->DI, m, dux_dx, dux_dy, duy_dx, duy_dy, A8, A9);
+}
+
+// A structure-of-arrays buffer seen through one buffer resource: plane i of a cell is at
+// byte offset i * plane_bytes (scalar offset operand) + the cell's byte offset (vector
+// operand).  The whole buffer must lie within 4 GiB of its base.
+struct Soa {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t plane_bytes;
+};
+
+__device__ __forceinline__ Soa soa(const double* base, int64_t plane) {
+    Soa s;
+    s.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, -1, 0x00020000);
+    s.plane_bytes = (uint32_t)(plane * 8);
+    return s;
+}
+
+// load/store at scalar byte offset `soff` (e.g. a plane) plus vector byte offset `voff`
+__device__ __forceinline__ double ld(const Soa& b, uint32_t soff, uint32_t voff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void st(const Soa& b, uint32_t soff, uint32_t voff, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 0);
+}
+
+// An opaque copy of a wave-uniform value.  Offsets derived from different copies are not
+// merged by the compiler, so the 24 plane offsets of one phase are not kept alive (and
+// spilled) through the other phase.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// the 24 values of one cell; the plane step is added to the vector offset
+__device__ __forceinline__ void load_cell(const Soa& f, uint32_t off, double v[NV]) {
+    const uint32_t pb = opaque(f.plane_bytes);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        v[i] = ld(f, 0u, off);
+        off += pb;
+    }
 }
 
 // neighbour index along one axis with the boundary rule (periodic wrap or clamp)

@@ -50,48 +50,6 @@ __device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int
     return s;
 }
 
-// A structure-of-arrays buffer seen through one buffer resource: plane i of a cell is at
-// byte offset i * plane_bytes (scalar offset operand) + the cell's byte offset (vector
-// operand).  The whole buffer must lie within 4 GiB of its base.
-struct Soa {
-    __amdgpu_buffer_rsrc_t r;
-    uint32_t plane_bytes;
-};
-
-__device__ __forceinline__ Soa soa(const double* base, int64_t plane) {
-    Soa s;
-    s.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, -1, 0x00020000);
-    s.plane_bytes = (uint32_t)(plane * 8);
-    return s;
-}
-
-// load/store at scalar byte offset `soff` (e.g. a plane) plus vector byte offset `voff`
-__device__ __forceinline__ double ld(const Soa& b, uint32_t soff, uint32_t voff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ void st(const Soa& b, uint32_t soff, uint32_t voff, double v) {
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 0);
-}
-
-// An opaque copy of a wave-uniform value.  Offsets derived from different copies are not
-// merged by the compiler, so the 24 plane offsets of one phase are not kept alive (and
-// spilled) through the other phase.
-__device__ __forceinline__ uint32_t opaque(uint32_t x) {
-    asm volatile("" : "+s"(x));
-    return x;
-}
-
-// the 24 values of one cell; the plane step is added to the vector offset
-__device__ __forceinline__ void load_cell(const Soa& f, uint32_t off, double v[NV]) {
-    const uint32_t pb = opaque(f.plane_bytes);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        v[i] = ld(f, 0u, off);
-        off += pb;
-    }
-}
-
 // one full time step of one cell (all inputs at level n); M holds the matrix blocks.
 // AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1.
 template <bool AMOD, bool CHEM, bool GEXP>

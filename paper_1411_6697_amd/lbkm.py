@@ -78,6 +78,7 @@ SIGNATURES = {
     "lbkm_batch_step": [_P, ctypes.c_int64],
     "lbkm_batch_get_moments": [_P, _P, _P, _P, _P, _P, _P],
     "lbkm_batch_total_cells": [_P, ctypes.POINTER(ctypes.c_int64)],
+    "lbkm_batch_status": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
 }
 
 _lib = None
@@ -231,6 +232,88 @@ class Sim:
         v = ctypes.c_int64()
         self._call("lbkm_get_step_count", ctypes.byref(v))
         return v.value
+
+
+class Batch:
+    """Ragged batch of 1D instances advanced together (library-owned packed state)."""
+
+    def __init__(self, nx: Sequence[int], dx: float, dt: float, dvm: Sequence[float], device="cuda:0"):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.nx = [int(v) for v in nx]
+        self.offsets = np.concatenate([[0], np.cumsum(self.nx)]).astype(np.int64)
+        g = Grid(nx=1, ny=1, dx=dx, dy=dx, dt=dt, bc_x=LBKM_BC_OUTFLOW, bc_y=LBKM_BC_PERIODIC,
+                 dvm=Dvm(*[float(v) for v in dvm]))
+        arr = (ctypes.c_int32 * len(self.nx))(*self.nx)
+        h = ctypes.c_void_p()
+        st = self.lib.lbkm_batch_create(ctypes.c_int32(len(self.nx)), arr, ctypes.byref(g),
+                                        _stream_handle(self.device), ctypes.byref(h))
+        self.h = h
+        if st != 0:
+            msg = self.lib.lbkm_last_error(h).decode() if h.value else "lbkm_batch_create failed"
+            self.close()
+            raise LbkmError(st, msg)
+        self.total = int(self.offsets[-1])
+
+    _call = Sim._call
+    close = Sim.close
+    __del__ = Sim.__del__
+
+    def set_params(self, R, gamma: float, Pr=None, Q: float = 0.0, omega1: float = 0.0,
+                   omega2: float = 0.0, m: float = 1.0, n: float = 1.0, T_ig: float = 1.1):
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(len(self.nx), 24)
+        S = R.ctypes.data_as(_D)
+        P = None
+        if Pr is not None:
+            Pr = np.ascontiguousarray(Pr, dtype=np.float64).reshape(len(self.nx))
+            P = Pr.ctypes.data_as(_D)
+        r = Rates(omega1=omega1, omega2=omega2, m=m, n=n, T_ig=T_ig)
+        self._call("lbkm_batch_set_params", S, P, ctypes.c_double(gamma), ctypes.c_double(Q),
+                   ctypes.byref(r))
+
+    def init_fields(self, rho, ux, uy, T, lam):
+        t = [_dev(a, self.device).reshape(self.total).contiguous() for a in (rho, ux, uy, T, lam)]
+        self._call("lbkm_batch_init_fields", *[_ptr(a) for a in t])
+        self._keep = t
+
+    def autotune(self) -> int:
+        v = ctypes.c_int32()
+        self._call("lbkm_batch_autotune", ctypes.byref(v))
+        return v.value
+
+    def step(self, n: int = 1):
+        self._call("lbkm_batch_step", ctypes.c_int64(int(n)))
+
+    def status(self):
+        """(work-groups, work-groups per CU); raises if a neighbour wait ran out."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        self._call("lbkm_batch_status", ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    def moments(self) -> Dict[str, torch.Tensor]:
+        out = {k: torch.empty(self.total, dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "T", "p", "lam")}
+        self._call("lbkm_batch_get_moments", *[_ptr(out[k]) for k in ("rho", "ux", "uy", "T", "p", "lam")])
+        return out
+
+    def split(self, packed: torch.Tensor):
+        """Per-instance views of a packed field."""
+        return [packed[self.offsets[k]:self.offsets[k + 1]] for k in range(len(self.nx))]
+
+
+def batch_from_spec(spec, device="cuda:0", instances=None) -> Batch:
+    """Create, parameterise and initialise a Batch from a workloads.BatchSpec (or a subset
+    of its instances)."""
+    idx = list(range(len(spec.nx))) if instances is None else list(instances)
+    ws = [spec.instance(k) for k in idx]
+    b0 = spec.base
+    b = Batch([w.nx for w in ws], b0.dx, b0.dt, b0.dvm, device=device)
+    b.set_params(np.stack([np.asarray(w.R, dtype=np.float64) for w in ws]), b0.gamma, None, b0.Q,
+                 b0.omega1, b0.omega2, b0.m, b0.n, b0.T_ig)
+    F = [w.fields() for w in ws]
+    b.init_fields(*[np.concatenate([np.asarray(f[k], dtype=np.float64).reshape(-1) for f in F])
+                    for k in ("rho", "ux", "uy", "T", "lam")])
+    return b
 
 
 def sim_from_workload(w, device="cuda:0", pitch=None, fields=None) -> Sim:

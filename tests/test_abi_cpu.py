@@ -135,3 +135,30 @@ def test_gamma_maps_to_integer_internal_dof():
         assert _set_params(h, [1e5] * 24, gamma=1.0 + 2.0 / 7.0)[0] == 0   # I = 5
     finally:
         _destroy(h)
+
+
+def _batch_create(nx, g=None):
+    lib = L.load()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int32 * max(len(nx), 1))(*nx)
+    st = lib.lbkm_batch_create(len(nx), arr, ctypes.byref(g or _grid()), None, ctypes.byref(h))
+    msg = lib.lbkm_last_error(h).decode() if h.value else ""
+    return st, h, msg
+
+
+@pytest.mark.parametrize("nx,g,status", [([], None, -1), ([5, 0, 7], None, -1), ([3, -2], None, -1),
+                                         ([2 ** 27, 2 ** 27], None, -1),
+                                         ([10], _grid(dvm=(2.0, 2.0, 1.2, 1.0, 1.0, 0.5)), -2),
+                                         ([10], _grid(dt=-1.0), -1)])
+def test_batch_create_validates_on_the_host(nx, g, status):
+    st, h, msg = _batch_create(nx, g)
+    try:
+        assert st == status, msg
+        if h.value:
+            assert msg
+            # a batched context refuses the single-grid calls
+            lib = L.load()
+            assert lib.lbkm_step(h, 1) == -5
+            assert lib.lbkm_bind_buffers(h, 1, 2, 3, 4, 64) == -5
+    finally:
+        _destroy(h)
