@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbkm.so")
-SOURCES = ["dvm_host.cpp", "abi.cpp", "kernels.hip", "step.hip", "batch.hip", "stubs.cpp"]
+SOURCES = ["dvm_host.cpp", "abi.cpp", "kernels.hip", "step.hip", "batch.hip", "adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -345,6 +345,7 @@ lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->out8) (void)hipFree(ctx->out8);
     if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->adj_scratch) (void)hipFree(ctx->adj_scratch);
     delete ctx;
     return LBKM_OK;
 }

@@ -32,6 +32,8 @@ struct lbkm_ctx {
     double* out8 = nullptr;
     int* flag = nullptr;
     lbkm::BatchState* batch = nullptr;
+    double* adj_scratch = nullptr;     // adjoint step: U, W planes and parameter partials
+    int64_t adj_scratch_n = 0;
     std::string err;
 };
 

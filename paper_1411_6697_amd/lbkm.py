@@ -233,6 +233,104 @@ class Sim:
         self._call("lbkm_get_step_count", ctypes.byref(v))
         return v.value
 
+    # -- adjoint (dense [24][ny][nx] / [ny][nx] device tensors)
+    def set_theta(self, theta, gamma: float, m: float = 1.0, n: float = 1.0, T_ig: float = 1.1):
+        """Parameters from theta = (R_1..R_24, Q, omega_1, omega_2), with R_8, R_9 taken as
+        given (the parameter vector of the gradient entry points)."""
+        th = [float(v) for v in (theta.detach().cpu().tolist() if isinstance(theta, torch.Tensor) else theta)]
+        if len(th) != NUM_GRAD:
+            raise ValueError(f"theta needs {NUM_GRAD} entries")
+        self.set_params(th[:24], gamma, 0.0, th[24], th[25], th[26], m, n, T_ig)
+
+    def adjoint_step(self, f_n, lam_n, af_np1, alam_np1, grad: torch.Tensor):
+        """Adjoint of one step: returns (af_n, alam_n) and adds the parameter gradient of
+        this step to grad (27 doubles on the device)."""
+        af_n = torch.empty_like(af_np1)
+        alam_n = torch.empty_like(alam_np1)
+        self._call("lbkm_adjoint_step", _ptr(f_n), _ptr(lam_n), _ptr(af_np1), _ptr(alam_np1),
+                   _ptr(af_n), _ptr(alam_n), _ptr(grad))
+        return af_n, alam_n
+
+    def adjoint_init(self, rho, ux, uy, T, af):
+        t = [_dev(a, self.device).reshape(self.ny, self.nx).contiguous() for a in (rho, ux, uy, T)]
+        out = [torch.empty(self.ny, self.nx, dtype=torch.float64, device=self.device) for _ in range(4)]
+        self._call("lbkm_adjoint_init", *[_ptr(a) for a in t], _ptr(af), *[_ptr(o) for o in out])
+        self._keep = t
+        return tuple(out)
+
+    def tne_loss(self, f, grad: bool = True):
+        """L = sum_cells sum_{k=5..24} Delta_k^2 of a dense state, and dL/df if grad."""
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(f) if grad else None
+        self._call("lbkm_tne_loss", _ptr(f), _ptr(loss), _ptr(g))
+        return loss[0], g
+
+
+NUM_GRAD = 27   # R_1..R_24, Q, omega_1, omega_2
+
+
+class LBKMRun(torch.autograd.Function):
+    """(f^N, lambda^N) after `steps` steps from the initial fields, differentiable with
+    respect to theta = (R_1..R_24, Q, omega_1, omega_2) and the initial rho, u_x, u_y, T,
+    lambda.  The forward pass keeps a checkpoint every `every` steps; the backward pass
+    re-runs each segment from its checkpoint, keeps the segment's states, and applies the
+    library's adjoint step to them in reverse order.  The Sim must not be used by anything
+    else between the forward and the backward pass."""
+
+    @staticmethod
+    def forward(ctx, theta, rho, ux, uy, T, lam, sim: "Sim", steps: int, gamma: float,
+                every: int = 50, m: float = 1.0, n: float = 1.0, T_ig: float = 1.1):
+        sim.set_theta(theta, gamma, m, n, T_ig)
+        sim.init_fields(rho, ux, uy, T, lam)
+        ckpts, done = [], 0
+        while done < steps:
+            ckpts.append(sim.get_state())
+            k = min(every, steps - done)
+            sim.step(k)
+            done += k
+        fN, lN = sim.get_state()
+        ctx.sim, ctx.ckpts, ctx.steps, ctx.every = sim, ckpts, steps, every
+        ctx.fields = tuple(_dev(a, sim.device).reshape(sim.ny, sim.nx) for a in (rho, ux, uy, T))
+        ctx.theta_meta = (theta.dtype, theta.device)
+        return fN, lN
+
+    @staticmethod
+    def backward(ctx, gf, gl):
+        sim = ctx.sim
+        kw = dict(dtype=torch.float64, device=sim.device)
+        af = gf.contiguous() if gf is not None else torch.zeros(24, sim.ny, sim.nx, **kw)
+        al = gl.contiguous() if gl is not None else torch.zeros(sim.ny, sim.nx, **kw)
+        grad = torch.zeros(NUM_GRAD, **kw)
+        for seg in reversed(range(len(ctx.ckpts))):
+            f0, l0 = ctx.ckpts[seg]
+            k = min(ctx.every, ctx.steps - seg * ctx.every)
+            sim.set_state(f0, l0)
+            stash = [(f0, l0)]
+            for _ in range(k - 1):
+                sim.step(1)
+                stash.append(sim.get_state())
+            for s in reversed(range(k)):
+                af, al = sim.adjoint_step(stash[s][0], stash[s][1], af, al, grad)
+            del stash
+        arho, aux, auy, aT = sim.adjoint_init(*ctx.fields, af)
+        dt, dev = ctx.theta_meta
+        return (grad.to(dtype=dt, device=dev), arho, aux, auy, aT, al) + (None,) * 7
+
+
+class TNELoss(torch.autograd.Function):
+    """L = sum_cells sum_{k=5..24} Delta_k^2 of a dense state f (Sec. VI)."""
+
+    @staticmethod
+    def forward(ctx, f, sim: "Sim"):
+        loss, g = sim.tne_loss(f.contiguous(), grad=True)
+        ctx.save_for_backward(g)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return g * gout, None
+
 
 class Batch:
     """Ragged batch of 1D instances advanced together (library-owned packed state)."""

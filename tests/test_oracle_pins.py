@@ -541,3 +541,56 @@ def test_detonation_plateau_is_the_cj_state():
     assert abs(speed - cj["D"]) < 0.06 * cj["D"]
     assert m["p"][0].max().item() > 1.3 * cj["p"]                     # von Neumann spike
     assert m["lam"].max().item() <= 1.0 + 1e-12 and m["lam"][0, -1].item() == 0.0
+
+
+def test_oracle_gradient_matches_its_own_central_differences():
+    """Reverse-mode differentiation of the oracle (the reference for the GPU adjoint) agrees
+    with central differences of the oracle's forward run.  Loss: the non-equilibrium sum
+    sum sum_{k>=5} Delta_k^2 plus sum lambda^2 after 4 steps of an 8 x 4 grid (outflow in x,
+    periodic in y) with random O(1) fields, so that the reaction runs in every cell, A_hat
+    is active (R_8 = R_9 = 2 R_5) and the minmod switch points lie far from the state.
+    Derivatives with respect to R_5, R_8, R_9, R_10, R_21, Q, omega_1, omega_2 (relative
+    step 1e-4) and along random perturbations of the initial T and lambda (step 1e-5)."""
+    w = W.adjoint_strip(nx=8, ny=4, steps=4)
+    g = np.random.default_rng(21)
+    F0 = dict(rho=1.0 + 0.2 * g.random((4, 8)), ux=0.1 * g.standard_normal((4, 8)),
+              uy=0.1 * g.standard_normal((4, 8)), T=1.25 + 0.3 * g.random((4, 8)),
+              lam=0.05 + 0.9 * g.random((4, 8)))
+
+    def loss(theta, F, grad=False):
+        P = oracle_params(w)
+        tab = oracle.make_tables(P)
+        tab.R = torch.tensor(theta[:24], dtype=torch.float64, requires_grad=grad)
+        tab.Q = torch.tensor(theta[24], dtype=torch.float64, requires_grad=grad)
+        tab.omega1 = torch.tensor(theta[25], dtype=torch.float64, requires_grad=grad)
+        tab.omega2 = torch.tensor(theta[26], dtype=torch.float64, requires_grad=grad)
+        T = torch.tensor(F["T"], dtype=torch.float64, requires_grad=grad)
+        lam0 = torch.tensor(F["lam"], dtype=torch.float64, requires_grad=grad)
+        f = oracle.init_f(torch.from_numpy(F["rho"]), torch.from_numpy(F["ux"]),
+                          torch.from_numpy(F["uy"]), T, P, tab)
+        f, lam = oracle.run(f, lam0, P, tab, w.steps)
+        delta, _ = oracle.tne(f, P, tab)
+        L = (delta * delta).sum() + (lam * lam).sum()
+        if not grad:
+            return float(L)
+        L.backward()
+        gth = np.concatenate([tab.R.grad.numpy(), [float(tab.Q.grad), float(tab.omega1.grad),
+                                                   float(tab.omega2.grad)]])
+        return gth, T.grad.numpy(), lam0.grad.numpy()
+
+    th = np.array(list(w.R) + [w.Q, w.omega1, w.omega2], dtype=np.float64)
+    gth, gT, gl = loss(th, F0, grad=True)
+    h = 1e-4
+    for k in (4, 7, 8, 9, 20, 24, 25, 26):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h * th[k]
+        tm[k] -= h * th[k]
+        fd = (loss(tp, F0) - loss(tm, F0)) / (2 * h * th[k])
+        assert abs(fd - gth[k]) <= 1e-5 * abs(fd), (k, gth[k], fd)
+    d = np.random.default_rng(5).standard_normal(F0["T"].shape)
+    hf = 1e-5
+    for name, gv in (("T", gT), ("lam", gl)):
+        ad = float(np.sum(gv * d))
+        fd = (loss(th, dict(F0, **{name: F0[name] + hf * d}))
+              - loss(th, dict(F0, **{name: F0[name] - hf * d}))) / (2 * hf)
+        assert abs(fd - ad) <= 1e-6 * abs(fd), (name, ad, fd)
