@@ -4,9 +4,13 @@ Workload: the doubly periodic 2048 x 2048 Kelvin-Helmholtz configuration (reacti
 the inert Q = 0 run is reported beside it), float64.  One step = one full time step of the
 method over the grid (macroscopic moments, f_hat = M f, equilibrium, A_hat, collision,
 chemistry and C_i, M^-1, NND streaming, forward Euler, lambda update), i.e. one launch of
-the fused step kernel.  Prints one JSON line.
+the fused step kernel.  Reported beside it on the same GPU: the batched form (128 ragged
+1D detonations, one persistent launch per graph replay) and the adjoint form (gradient of
+the non-equilibrium loss over a 2048 x 256 detonation strip, 500 steps, checkpoints every
+50), each against the plain step's time per cell-update.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
+                  [--no-inert] [--no-batched] [--no-adjoint]
 """
 
 from __future__ import annotations
@@ -116,6 +120,102 @@ def cpu_baseline(w, tile=1024, steps=8):
                       f"{steps} steps after 1 untimed step, {dt:.1f} s"}
 
 
+def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
+    """Config of 128 ragged 1D detonations: autotune, then `steps` steps as graph replays of
+    `chunk` steps each (one persistent launch per replay)."""
+    import torch
+    from paper_1411_6697_amd import lbkm
+    from paper_1411_6697_amd import workloads as W
+    spec = W.batched(steps=steps)
+    b = lbkm.batch_from_spec(spec)
+    cells_per_wg = b.autotune()
+    b.step(chunk)                                  # captures the replayed graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps // chunk):
+        b.step(chunk)
+    e1.record()
+    torch.cuda.synchronize()
+    wgs, per_cu = b.status()
+    ms = e0.elapsed_time(e1) / (steps // chunk * chunk)
+    mlups = b.total / (ms * 1e-3) / 1e6
+    ok = bool(torch.isfinite(b.moments()["rho"]).all())
+    # the same instances as separate single-grid runs, one launch per instance and step
+    sims = [lbkm.sim_from_workload(spec.instance(k)) for k in range(len(spec.nx))]
+    for s_ in sims:
+        s_.step(2)
+    torch.cuda.synchronize()
+    sep_steps = 20
+    t0 = time.perf_counter()
+    for _ in range(sep_steps):
+        for s_ in sims:
+            s_.step(1)
+    torch.cuda.synchronize()
+    sep_ms = (time.perf_counter() - t0) * 1e3 / sep_steps
+    del sims
+    gbs = BYTES_PER_CELL * b.total / (ms * 1e-3) / 1e9
+    return {"workload": f"batched_{len(spec.nx)}_detonations_nx_1000_8000_outflow", "instances": len(spec.nx),
+            "cells": int(b.total), "steps": steps // chunk * chunk, "ms_per_step": round(ms, 5),
+            "mlups": round(mlups, 2), "algorithmic_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ns_per_cell_update": round(ms * 1e6 / b.total, 5),
+            "vs_plain_step_time_per_cell": round(ms * 1e6 / b.total / ns_per_cell_plain, 3),
+            "work_groups": wgs, "work_groups_per_cu": per_cu, "cells_per_work_group": cells_per_wg,
+            "graph_steps_per_replay": chunk, "state_finite_after_run": ok,
+            "separate_launches_mlups": round(b.total / (sep_ms * 1e-3) / 1e6, 2)}
+
+
+def bench_adjoint(ns_per_cell_plain):
+    """Gradient of the non-equilibrium loss of the 2048 x 256 strip after 500 steps with
+    respect to (R_1..R_24, Q, omega_1, omega_2) and the initial fields: checkpointed
+    forward, recomputation and the adjoint steps, wall time of the whole backward pass;
+    the adjoint step alone timed with events over 100 calls."""
+    import torch
+    from paper_1411_6697_amd import lbkm
+    from paper_1411_6697_amd import workloads as W
+    w = W.adjoint_strip()
+    cells = w.nx * w.ny
+    plain = lbkm.sim_from_workload(w)
+    ms_plain = time_steps(plain, 200, 10)
+    del plain
+    s = lbkm.Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.dvm, w.bc_x, w.bc_y)
+    F = w.fields()
+    theta = torch.tensor(list(w.R) + [w.Q, w.omega1, w.omega2], dtype=torch.float64, requires_grad=True)
+    ts = [torch.tensor(F[k], dtype=torch.float64, device=s.device, requires_grad=True)
+          for k in ("rho", "ux", "uy", "T", "lam")]
+    times = []
+    for _ in range(2):                             # the first pass warms up allocations
+        theta.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fN, lN = lbkm.LBKMRun.apply(theta, *ts, s, w.steps, w.gamma, 50, w.m, w.n, w.T_ig)
+        loss = lbkm.TNELoss.apply(fN, s)
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    f, lam = s.get_state()
+    af = torch.ones_like(f)
+    al = torch.ones_like(lam)
+    grad = torch.zeros(lbkm.NUM_GRAD, dtype=torch.float64, device=s.device)
+    s.adjoint_step(f, lam, af, al, grad)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 100
+    e0.record()
+    for _ in range(reps):
+        af, al = s.adjoint_step(f, lam, af, al, grad)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / reps
+    return {"workload": f"detonation_strip_{w.nx}x{w.ny}_{w.steps}_steps_checkpoint_50",
+            "loss": float(loss), "gradient_wall_s": round(times[-1], 4),
+            "plain_step_ms": round(ms_plain, 5), "adjoint_step_ms": round(ms_adj, 5),
+            "adjoint_step_vs_plain_step": round(ms_adj / ms_plain, 3),
+            "gradient_vs_plain_run": round(times[-1] / (w.steps * ms_plain * 1e-3), 3),
+            "plain_ns_per_cell_update": round(ms_plain * 1e6 / cells, 5),
+            "vs_kh_plain_step_time_per_cell": round(ms_adj * 1e6 / cells / ns_per_cell_plain, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +224,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-inert", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -157,7 +259,7 @@ def main():
     ceiling = copy_ceiling_gbs()
     traffic = measured_traffic()
     out = {
-        "metric": "MLUPS (cell updates/s) FP64 at 2048^2",
+        "metric": "MLUPS (cell updates/s) FP64 at 2048\u00b2; batched & adjoint vs plain step time",
         "value": round(value, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -179,6 +281,13 @@ def main():
                      "copy_kernel_gbs": round(ceiling, 1)},
         "inert_Q0": inert,
     }
+    ns_cell = ms * 1e6 / cells
+    if not args.no_batched:
+        out["batched"] = bench_batched(ns_cell)
+        torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(ns_cell)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
