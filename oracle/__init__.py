@@ -20,7 +20,38 @@ physics  : independent physics references used to pin the model: the exact
            von Neumann states, and Gauss-Hermite moments of the continuous
            Maxwellian.
 
-Parity status of each function is stated in its docstring.
+What pins each function (tests/test_oracle_pins.py, checked against the paper or
+the mathematics, never against the oracle itself):
+
+  velocity_set          geometry of the three 8-velocity groups
+  moment_matrix,        exact rational inverse; M^-1 M = I; equilibrium recovery
+  inverse_moment_matrix
+  equilibrium_moments   Gauss-Hermite moments of the continuous Maxwellian (all 24
+                        rows); the printed rows 14/16 without T fail that check
+  macroscopic           equilibrium recovery; a uniform state is a fixed point
+  collision             mass, momentum and energy conservation; closed-form decay
+                        (1 - R_k dt)^n of every non-conserved moment (pins forward
+                        Euler and the R-to-moment mapping)
+  modification_terms    its sign: only the chosen sign makes the viscous heating
+                        independent of R_8 (Chapman-Enskog, Sec. III)
+  cochran_increment     exact solution of the rate equation (against a fine RK4);
+                        homogeneous heating 2 Q dlambda / (D + I)
+  chemical_term         moments k = 1..9 equal the printed C_hat (Sec. II); the
+                        energy budget on a periodic grid.  Moments k >= 10:
+                        parity unpinned (the paper prints no value for them)
+  nnd_derivative,       exact on linear data, zero on constants, upwind, second
+  streaming             order on smooth monotone data, mirror symmetry
+  step, run, init_f     Sod against the exact Riemann solution; the CJ plateau of a
+                        detonation; shear-wave decay at the Chapman-Enskog
+                        viscosity; conservation on periodic grids
+  tne, reductions       readout identities (Sec. VI)
+  (reverse-mode AD)     the gradient of a run agrees with central differences of
+                        the oracle's forward run
+  physics.*             the paper's CJ numbers (tests/golden/cj_state.txt); Rankine-
+                        Hugoniot jump conditions of the exact Riemann solution
+
+Inputs that no pin can fix: the Cochran rate constants omega_1, omega_2 (never
+printed; a project choice of the workloads).
 """
 
 from .dvm import DVM, velocity_set, moment_matrix, inverse_moment_matrix
