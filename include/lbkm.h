@@ -220,6 +220,11 @@ lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const doubl
  * receives the resulting cells per work-group.  Synchronous. */
 lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg);
 
+/* Fix the launch shape instead of autotuning: wgs_per_cu work-groups per compute unit
+ * (1..16).  LBKM_EINVAL if the kernel's occupancy does not allow that many (the shape
+ * then falls back to the largest allowed).  Synchronous. */
+lbkm_status lbkm_batch_set_launch(lbkm_ctx* ctx, int32_t wgs_per_cu);
+
 /* Advance every instance n steps, 0 <= n < 2^31 (asynchronous; replays a captured
  * graph, one per buffer parity and n). */
 lbkm_status lbkm_batch_step(lbkm_ctx* ctx, int64_t n);

@@ -12,9 +12,10 @@
 // instance boundaries, so each segment's rates are wave-uniform (scalar loads).  For each
 // step a work-group updates its range from buffer `cur` into the other buffer; it may start
 // step s+1 once both neighbouring ranges have completed step s (then their step-s values,
-// its halo, are final, and they no longer read the buffer it is about to overwrite).  The
-// counters are published with device-scope release after a device-scope fence and read
-// with acquire, which invalidates the reader's L1.  Waiting is bounded: past the spin
+// its halo, are final, and they no longer read the buffer it is about to overwrite).  After
+// a work-group barrier, thread 0 publishes the counter with one device-scope release store;
+// a reader polls with relaxed loads and then issues one device-scope acquire fence.
+// Waiting is bounded: past the spin
 // limit the kernel records an error and every work-group returns, so the launch always
 // drains.
 
@@ -73,13 +74,16 @@ struct BatchState {
 
 namespace {
 
+// Poll a neighbour's completed-step counter with relaxed loads (the caller issues one
+// acquire fence once both neighbours are ready, so the caches are invalidated once per
+// step rather than once per poll).
 __device__ __forceinline__ bool wait_counter(const uint32_t* flags, int nb, int nwg, uint32_t want,
                                              const int32_t* err) {
     if (nb < 0 || nb >= nwg) return true;
     for (int k = 0; k < kSpinLimit; ++k) {
-        if (__hip_atomic_load(flags + nb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
+        if (__hip_atomic_load(flags + nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) return true;
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
     return false;
 }
@@ -147,7 +151,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
                                                          double* f0, double* f1, double* l0, double* l1,
                                                          int64_t steps, int parity, uint32_t* flags,
                                                          int32_t* err) {
-    const int w = blockIdx.x;
+    // Ranges are dealt to the XCDs in contiguous bands (the hardware hands consecutive
+    // work-group ids to the eight XCDs in turn), so neighbouring ranges, which exchange
+    // halos every step, mostly share an L2.  nwg is a multiple of 8 or below 8.
+    const int b8 = (int)blockIdx.x;
+    const int w = nwg >= 8 ? (b8 % 8) * (nwg / 8) + b8 / 8 : b8;
     const int sbeg = wg_seg[w], send = wg_seg[w + 1];
     __shared__ int32_t stop;
     // the descriptors are swapped after every step (selecting them by step parity inside
@@ -161,6 +169,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
                 const bool ok = wait_counter(flags, w - 1, nwg, want, err) &&
                                 wait_counter(flags, w + 1, nwg, want, err);
                 if (!ok) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 stop = ok ? 0 : 1;
             }
             __syncthreads();
@@ -175,7 +184,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
                 if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, j, F, G, L, Lo);
             }
         }
-        __threadfence();               // this thread's stores are visible device-wide
+        // The barrier orders every thread's stores before thread 0's release (cumulative),
+        // so one device-scope release per work-group publishes the whole range.
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(flags + w, (uint32_t)(s + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -251,6 +261,7 @@ lbkm_status build_decomposition(lbkm_ctx* ctx, int wgs_per_cu) {
     const int per_cu = std::min(wgs_per_cu, occ);
     int nwg = std::max(1, b->cus * per_cu);
     nwg = (int)std::min<int64_t>(nwg, std::max<int64_t>(1, b->total / 64));
+    if (nwg >= 8) nwg -= nwg % 8;                       // whole XCD bands (see k_batch)
     std::vector<BatchSeg> segs;
     std::vector<int32_t> wg_seg(nwg + 1, 0);
     int k = 0;
@@ -516,6 +527,18 @@ lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg) {
     if (e != hipSuccess) return hip_fail(ctx, e, "batch autotune");
     if (st != LBKM_OK) return st;
     if (cells_per_wg) *cells_per_wg = (int32_t)((b->total + b->nwg - 1) / b->nwg);
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_batch_set_launch(lbkm_ctx* ctx, int32_t wgs_per_cu) {
+    lbkm_status st = batch_ready(ctx, false);
+    if (st != LBKM_OK) return st;
+    if (wgs_per_cu < 1 || wgs_per_cu > 16) return fail(ctx, LBKM_EINVAL, "wgs_per_cu must be in 1..16");
+    st = build_decomposition(ctx, wgs_per_cu);
+    if (st != LBKM_OK) return st;
+    if (ctx->batch->wgs_per_cu != wgs_per_cu)
+        return fail(ctx, LBKM_EINVAL, "the kernel's occupancy allows only " +
+                                          std::to_string(ctx->batch->wgs_per_cu) + " work-groups per CU");
     return LBKM_OK;
 }
 

@@ -350,6 +350,12 @@ __device__ __forceinline__ void st(const Soa& b, uint32_t soff, uint32_t voff, d
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 0);
 }
+// The same with the non-temporal cache policy: the new state is not read again within the
+// step, so its lines should not displace the stencil data that the caches are reusing.
+__device__ __forceinline__ void st_stream(const Soa& b, uint32_t soff, uint32_t voff, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 2);
+}
 
 // An opaque copy of a wave-uniform value.  Offsets derived from different copies are not
 // merged by the compiler, so the 24 plane offsets of one phase are not kept alive (and

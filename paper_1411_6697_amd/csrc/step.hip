@@ -114,14 +114,14 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
             if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)) * idy);
-            st(G, so, s.c, f0 + dt * (src[8 * g + d] - adv));
+            st_stream(G, so, s.c, f0 + dt * (src[8 * g + d] - adv));
         }
     }
     const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
                                     : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
     const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
                                     : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
-    st(Lo, 0u, s.c, lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+    st_stream(Lo, 0u, s.c, lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -234,12 +234,12 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
             if (DUX[d] < 0) adv -= v * (nnd_neg(q[-1], f0, q[1], q[2]) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]) * idy);
-            if (inside) st(G, (uint32_t)i * pb, out_off, f0 + dt * (src[i] - adv));
+            if (inside) st_stream(G, (uint32_t)i * pb, out_off, f0 + dt * (src[i] - adv));
         } else if (inside) {
             const double dlx = (m.ux > 0.0) ? nnd_pos(q[-2], q[-1], f0, q[1]) : nnd_neg(q[-1], f0, q[1], q[2]);
             const double dly = (m.uy > 0.0) ? nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW])
                                             : nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
-            st(Lo, 0u, out_off, f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+            st_stream(Lo, 0u, out_off, f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
         }
     }
 }

@@ -79,6 +79,7 @@ SIGNATURES = {
     "lbkm_batch_get_moments": [_P, _P, _P, _P, _P, _P, _P],
     "lbkm_batch_total_cells": [_P, ctypes.POINTER(ctypes.c_int64)],
     "lbkm_batch_status": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "lbkm_batch_set_launch": [_P, ctypes.c_int32],
 }
 
 _lib = None
@@ -378,6 +379,9 @@ class Batch:
         v = ctypes.c_int32()
         self._call("lbkm_batch_autotune", ctypes.byref(v))
         return v.value
+
+    def set_launch(self, wgs_per_cu: int):
+        self._call("lbkm_batch_set_launch", ctypes.c_int32(int(wgs_per_cu)))
 
     def step(self, n: int = 1):
         self._call("lbkm_batch_step", ctypes.c_int64(int(n)))
