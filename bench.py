@@ -176,6 +176,7 @@ def bench_adjoint(ns_per_cell_plain):
     w = W.adjoint_strip()
     cells = w.nx * w.ny
     plain = lbkm.sim_from_workload(w)
+    plain.autotune()
     ms_plain = time_steps(plain, 200, 10)
     del plain
     s = lbkm.Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.dvm, w.bc_x, w.bc_y)
@@ -240,6 +241,7 @@ def main():
     w = W.kh(n=args.n, steps=args.steps, reactive=True)
     cells = w.nx * w.ny
     sim = lbkm.sim_from_workload(w)
+    launch = sim.autotune()                     # launch shape: tile, LDS staging, tile order
     ms = time_steps(sim, args.steps, args.warmup)
     ok = sim.check()
     del sim
@@ -250,6 +252,7 @@ def main():
     if not args.no_inert:
         w0 = W.kh(n=args.n, steps=args.steps, reactive=False)
         s0 = lbkm.sim_from_workload(w0)
+        s0.autotune()
         ms0 = time_steps(s0, args.steps, args.warmup)
         del s0
         torch.cuda.empty_cache()
@@ -273,6 +276,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"kelvin_helmholtz_{w.nx}x{w.ny}_reactive_Q1_periodic",
                    "nx": w.nx, "ny": w.ny, "dt": w.dt, "velocities": "D2V24",
+                   "launch": {"tile": [launch[0], launch[1]], "lds": launch[2], "column_bands": launch[3]},
                    "state_finite_after_run": bool(ok)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -144,6 +144,18 @@ lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam);
  * launch shape (bitwise). */
 lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t lds);
 
+/* Order in which the tiles are dealt to the eight XCDs: vertical = 1 gives each XCD a
+ * contiguous band of tile columns (used only when their number divides by eight),
+ * vertical = 0 (the default) a band of tile rows.  Results do not depend on it. */
+lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical);
+
+/* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
+ * orders for a few steps from the current state, keeps the fastest, and restores the
+ * state and the step count (the trial steps run on the bound buffers; a temporary copy
+ * of the state is allocated).  Needs parameters and fields.  choice (host, 4 ints, may
+ * be NULL) receives tile_x, tile_y, lds, vertical.  Synchronous. */
+lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice);
+
 /* Host copies of the dense 24x24 moment matrix M (row k = moment m_{k+1}, column i =
  * velocity i) and of M^-1, both row-major, reassembled from the symmetry blocks the
  * kernels use; *cond (may be NULL) receives ||M||_inf ||M^-1||_inf.  Needs no device. */

@@ -230,8 +230,8 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     if (n < 0) return fail(ctx, LBKM_EINVAL, "n must be >= 0");
     for (int64_t k = 0; k < n; ++k) {
         const int a = ctx->cur, b = 1 - a;
-        hipError_t e = launch_step(ctx->d, ctx->step_variant, step_flags(ctx->h), ctx->grid.nx, ctx->grid.ny, ctx->f[a], ctx->f[b], ctx->lam[a],
-                                   ctx->lam[b], ctx->stream);
+        hipError_t e = launch_step(ctx->d, ctx->step_variant, step_flags(ctx->h), ctx->grid.nx, ctx->grid.ny,
+                                   ctx->f[a], ctx->f[b], ctx->lam[a], ctx->lam[b], ctx->tile_order, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
         ctx->cur = b;
         ++ctx->steps;
@@ -316,6 +316,75 @@ lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t
             return LBKM_OK;
         }
     return fail(ctx, LBKM_EINVAL, "unsupported step tile shape");
+}
+
+lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
+    if (!ctx) return LBKM_EINVAL;
+    if (vertical != 0 && vertical != 1) return fail(ctx, LBKM_EINVAL, "vertical must be 0 or 1");
+    ctx->tile_order = vertical;
+    return LBKM_OK;
+}
+
+lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    const int64_t cells = ctx->pitch * (int64_t)ctx->grid.ny;
+    const int cur = ctx->cur;
+    const int64_t steps0 = ctx->steps;
+    double* save = nullptr;
+    hipError_t e = hipMalloc((void**)&save, sizeof(double) * 25 * cells);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(save, ctx->f[cur], sizeof(double) * 24 * cells, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(save + 24 * cells, ctx->lam[cur], sizeof(double) * cells, hipMemcpyDeviceToDevice,
+                           ctx->stream);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    int best_v = ctx->step_variant, best_o = ctx->tile_order;
+    float best_ms = 1e30f;
+    const int trial = 4;
+    for (int v = 0; v < kNumStepVariants && e == hipSuccess; ++v)
+        for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+            ctx->step_variant = v;
+            ctx->tile_order = o;
+            st = lbkm_step(ctx, 1);                        // warm-up of this shape
+            if (st != LBKM_OK) break;
+            e = hipEventRecord(t0, ctx->stream);
+            if (e == hipSuccess) st = lbkm_step(ctx, trial);
+            if (st != LBKM_OK) break;
+            e = hipEventRecord(t1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best_v = v;
+                best_o = o;
+            }
+        }
+    ctx->step_variant = best_v;
+    ctx->tile_order = best_o;
+    ctx->cur = cur;
+    ctx->steps = steps0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->f[cur], save, sizeof(double) * 24 * cells, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->lam[cur], save + 24 * cells, sizeof(double) * cells, hipMemcpyDeviceToDevice,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (save) (void)hipFree(save);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+    if (st != LBKM_OK) return st;
+    if (choice) {
+        choice[0] = kStepVariants[best_v][0];
+        choice[1] = kStepVariants[best_v][1];
+        choice[2] = kStepVariants[best_v][2];
+        choice[3] = best_o;
+    }
+    return LBKM_OK;
 }
 
 lbkm_status lbkm_get_matrices(lbkm_ctx* ctx, double* M, double* Minv, double* cond) {

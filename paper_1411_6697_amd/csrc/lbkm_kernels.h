@@ -10,8 +10,10 @@ namespace lbkm {
 extern const int kStepVariants[][3];   // {tile_x, tile_y, lds} per launch variant (step.hip)
 extern const int kNumStepVariants;
 int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
+// vertical != 0: XCD-contiguous bands of tile columns (when the tile columns divide by
+// eight), else bands of tile rows
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
-                       double* fout, const double* lin, double* lout, hipStream_t st);
+                       double* fout, const double* lin, double* lout, int vertical, hipStream_t st);
 hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,
                        const double* uy, const double* T, const double* lam, double* f, double* lout,
                        hipStream_t st);

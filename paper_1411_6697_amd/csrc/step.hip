@@ -15,7 +15,8 @@
 //
 // Work-groups cover TX x TY tiles.  The hardware hands consecutive work-group ids to the
 // eight XCDs in turn; `tile_of` renumbers tiles so that XCD k walks the k-th contiguous
-// band of tiles in row-major order, keeping halo re-reads inside one XCD's L2.
+// band of tiles (a band of tile columns when their number divides by eight, else a band of
+// tile rows), keeping halo re-reads inside one XCD's L2.
 
 #include <hip/hip_runtime.h>
 
@@ -245,7 +246,17 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
 }
 
 // tile t of the XCD-aware order for work-group b; returns false past the last tile
-__device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int& tx, int& ty) {
+__device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical, int& tx, int& ty) {
+    if (vertical && gx % kXcds == 0) {
+        // vertical bands: XCD k owns tile columns [k gx/8, (k+1) gx/8) and walks them row
+        // by row, so the rows above and below a tile (its y halo) were fetched into the
+        // same L2 moments earlier; only the two-cell x halo at band edges crosses XCDs
+        const int cols = gx / kXcds, k = b % kXcds, i = b / kXcds;
+        tx = k * cols + i % cols;
+        ty = i / cols;
+        return ty * gx < ntiles;
+    }
+    // horizontal bands of tiles in row-major order
     const int per = (ntiles + kXcds - 1) / kXcds;
     const int t = (b % kXcds) * per + b / kXcds;
     if (t >= ntiles) return false;
@@ -257,9 +268,9 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int& tx, int&
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
 __global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
-                                                  double* __restrict__ lout, int gx, int ntiles) {
+                                                  double* __restrict__ lout, int gx, int ntiles, int vertical) {
     int tx, ty;
-    if (!tile_of(blockIdx.x, gx, ntiles, tx, ty)) return;
+    if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c->nx || y >= c->ny) return;
@@ -270,38 +281,38 @@ template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
 __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__ c,
                                                       const double* __restrict__ fin, double* __restrict__ fout,
                                                       const double* __restrict__ lin, double* __restrict__ lout,
-                                                      int gx, int ntiles) {
+                                                      int gx, int ntiles, int vertical) {
     __shared__ double patch[2 * Patch<TX, TY>::N];
     int tx, ty;
-    if (!tile_of(blockIdx.x, gx, ntiles, tx, ty)) return;
+    if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     step_tile_lds<TX, TY, AMOD, CHEM, GEXP>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, patch);
 }
 
 template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
-                        double* lout, hipStream_t st) {
+                        double* lout, int vertical, hipStream_t st) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
     if (LDS)
         hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
-                           fin, fout, lin, lout, gx, ntiles);
+                           fin, fout, lin, lout, gx, ntiles, vertical);
     else
         hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
-                           fout, lin, lout, gx, ntiles);
+                           fout, lin, lout, gx, ntiles, vertical);
     return hipGetLastError();
 }
 
 template <int TX, int TY, bool LDS>
 hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
-                        const double* lin, double* lout, hipStream_t st) {
+                        const double* lin, double* lout, int vertical, hipStream_t st) {
     switch (flags) {
-        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, st);
-        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
-        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, st);
+        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
     }
 }
 
@@ -318,14 +329,14 @@ int step_flags(const Consts& c) {
 }
 
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
-                       double* fout, const double* lin, double* lout, hipStream_t st) {
+                       double* fout, const double* lin, double* lout, int vertical, hipStream_t st) {
     switch (variant) {
-        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, st);
-        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, st);
+        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
     }
 }
 

@@ -65,6 +65,8 @@ SIGNATURES = {
     "lbkm_get_step_count": [_P, ctypes.POINTER(ctypes.c_int64)],
     "lbkm_get_matrices": [_P, _D, _D, _D],
     "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "lbkm_set_tile_order": [_P, ctypes.c_int32],
+    "lbkm_autotune": [_P, ctypes.POINTER(ctypes.c_int32)],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_tne_loss": [_P, _P, _P, _P],
@@ -228,6 +230,15 @@ class Sim:
 
     def set_tile(self, tile_x: int, tile_y: int, lds: int = 1):
         self._call("lbkm_set_tile", ctypes.c_int32(tile_x), ctypes.c_int32(tile_y), ctypes.c_int32(lds))
+
+    def set_tile_order(self, vertical: int):
+        self._call("lbkm_set_tile_order", ctypes.c_int32(int(vertical)))
+
+    def autotune(self):
+        """Pick the fastest launch shape on this device; returns (tile_x, tile_y, lds, vertical)."""
+        out = (ctypes.c_int32 * 4)()
+        self._call("lbkm_autotune", out)
+        return tuple(out[:])
 
     def step_count(self) -> int:
         v = ctypes.c_int64()

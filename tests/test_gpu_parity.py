@@ -193,25 +193,48 @@ VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 
 
 @pytest.mark.parametrize("w", [W.detonation(nx=333, ny=7, steps=30).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
                                                                          bc_y="outflow"),
-                               W.kh(n=2048, steps=30).with_(nx=130, ny=67)],
-                         ids=["det-amod-333x7", "kh-130x67"])
+                               W.kh(n=2048, steps=30).with_(nx=130, ny=67),
+                               W.kh(n=2048, steps=20).with_(nx=2040, ny=9)],
+                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9"])
 def test_launch_variants_give_bitwise_identical_results(w):
-    """Every compiled launch shape (LDS-staged or not) computes the same bits; the grids do
-    not divide into tiles and use both boundary rules."""
+    """Every compiled launch shape (LDS-staged or not) in both tile orders computes the same
+    bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the
+    column-band order is taken, with a ragged last tile column)."""
     F = {k: np.ascontiguousarray(v[:w.ny, :w.nx]) for k, v in (w.fields() if w.ny * w.nx < 1e5 else
                                                                   W.kh(n=2048).fields()).items()}
     ref = None
     for v in VARIANTS:
-        s = _lbkm().sim_from_workload(w, fields=F)
-        s.set_tile(*v)
-        s.step(w.steps)
-        m = s.moments()
-        torch.cuda.synchronize()
-        if ref is None:
-            ref = m
-        else:
-            for k in m:
-                assert torch.equal(m[k], ref[k]), (v, k)
+        for order in (0, 1):
+            s = _lbkm().sim_from_workload(w, fields=F)
+            s.set_tile(*v)
+            s.set_tile_order(order)
+            s.step(w.steps)
+            m = s.moments()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = m
+            else:
+                for k in m:
+                    assert torch.equal(m[k], ref[k]), (v, order, k)
+
+
+def test_autotune_restores_state_and_keeps_results():
+    """The launch-shape autotuner runs trial steps on the bound buffers; afterwards the
+    state and step count are those before it, and the run continues bitwise as without it."""
+    w = W.kh(n=2048, steps=12).with_(nx=512, ny=96)
+    F = {k: np.ascontiguousarray(v[:w.ny, :w.nx]) for k, v in W.kh(n=2048).fields().items()}
+    a = _lbkm().sim_from_workload(w, fields=F)
+    a.step(5)
+    choice = a.autotune()
+    print("autotuned launch shape:", choice, flush=True)
+    assert a.step_count() == 5
+    a.step(7)
+    b = _lbkm().sim_from_workload(w, fields=F)
+    b.step(12)
+    ma, mb = a.moments(), b.moments()
+    torch.cuda.synchronize()
+    for k in ma:
+        assert torch.equal(ma[k], mb[k]), k
 
 
 def test_larger_pitch_gives_bitwise_identical_results():
