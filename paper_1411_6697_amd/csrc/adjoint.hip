@@ -7,14 +7,14 @@
 //
 // One adjoint step is three passes over the grid (all arrays dense [plane][ny][nx]):
 //   k_adj_macro   rho, u_x, u_y of every cell (the neighbours' values are needed twice)
-//   k_adj_local   the transposed Jacobian of everything that is local to a cell: the
-//                 identity, collision (M, f_hat^eq, R, A_hat), chemistry (Cochran step and
+//   k_adj_local   the transposed Jacobian of everything that is local to a cell:
+//                 collision (M, f_hat^eq, R, A_hat), chemistry (Cochran step and
 //                 C_i), the velocity factor of the lambda advection; parameter gradients
 //                 (per work-group partial sums); the adjoints of the velocity gradients
 //                 inside A_hat, which belong to the neighbours (3 values per cell)
-//   k_adj_stream  the transposed NND streaming of f and lambda (a gather over the cells
-//                 whose stencil reaches this cell, boundary rules included) and the
-//                 neighbours' A_hat terms
+//   k_adj_stream  the identity of the Euler step, the transposed NND streaming of f and
+//                 lambda (a gather over the cells whose stencil reaches this cell, boundary
+//                 rules included) and the neighbours' A_hat terms
 // followed by a fixed-order reduction of the parameter partials.
 
 #include <hip/hip_runtime.h>
@@ -29,15 +29,26 @@ namespace {
 
 constexpr int kAdjThreads = 256;
 constexpr int kNumGrad = 27;      // d/dR_1..R_24, d/dQ, d/domega_1, d/domega_2
+constexpr int kNumLds = 23;       // the ones a cell can touch: R_5..R_24, Q, omega_1, omega_2
 
-// y = A^T x for a block stored column-major (At[k][r] = A[r][k]): y_k = sum_r At[k][r] x_r
+// y = A^T x for a block stored column-major (At[k][r] = A[r][k]): y_k = sum_r At[k][r] x_r.
+// Each stored column is read through the constant address space just before its dot
+// product: the copy of its address is tied to the previous result, so the compiler does
+// not hoist all N*N scalar loads to the top (which runs out of scalar registers).
 template <int N>
 __device__ __forceinline__ void matvec_t(const double (*At)[N], const double* x, double* y) {
+    typedef const __attribute__((address_space(4))) double cdouble;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
+        const double* col = At[k];
+        if (k == 0)
+            asm volatile("" : "+s"(col) : "v"(x[N - 1]));
+        else
+            asm volatile("" : "+s"(col) : "v"(y[k - 1]));
+        cdouble* A = (cdouble*)(const void*)col;
         double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < N; ++r) s = fma(At[k][r], x[r], s);
+        for (int r = 0; r < N; ++r) s = fma(A[r], x[r], s);
         y[k] = s;
     }
 }
@@ -155,15 +166,12 @@ __device__ __forceinline__ void macro_t(const Blocks& h, const Macro& m, double 
 // argument gets 1, a tie between equal arguments splits it in halves, the zero branch
 // gets nothing.
 __device__ __forceinline__ void minmod_sel(double a, double b, double& sa, double& sb) {
-    sa = 0.0;
-    sb = 0.0;
-    if (a > 0.0 && b > 0.0) {
-        sa = a < b ? 1.0 : (a > b ? 0.0 : 0.5);
-        sb = 1.0 - sa;
-    } else if (a < 0.0 && b < 0.0) {
-        sa = a > b ? 1.0 : (a < b ? 0.0 : 0.5);
-        sb = 1.0 - sa;
-    }
+    // branch-free: selects only
+    const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+    const bool a_smaller = fabs(a) < fabs(b);
+    const double wa = a == b ? 0.5 : (a_smaller ? 1.0 : 0.0);
+    sa = same ? wa : 0.0;
+    sb = same ? 1.0 - wa : 0.0;
 }
 
 // Stencil bookkeeping of the transposed NND operator along one axis for the cell at
@@ -250,6 +258,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_macro(const Consts* __restr
     U[2 * plane + at] = m.uy;
 }
 
+// Register pressure: the parameter gradients of each thread are kept in LDS (not in
+// registers); the collision part's contribution M^T h_bar (moments 5..24) is written out as
+// soon as it is known; the equilibrium adjoint is folded into (rho, u, T) adjoints right
+// after the collision part and again after the chemistry part; f_hat^eq is evaluated a
+// second time inside the chemistry branch instead of being kept alive.  The adjoints of the
+// conserved moments h_1..h_4 are handed to k_adj_stream (4 planes of W), which adds their
+// closed-form transpose M^T h_bar = h_1 + v_x h_2 + v_y h_3 + (v^2 + eta^2) h_4 together
+// with the identity term of the Euler step and the neighbours' contributions.
 __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restrict__ c,
                                                            const double* __restrict__ f,
                                                            const double* __restrict__ lam,
@@ -258,23 +274,27 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                                                            const double* __restrict__ U,
                                                            double* __restrict__ af0, double* __restrict__ al0,
                                                            double* __restrict__ Wout, double* __restrict__ part) {
-    __shared__ double sh[4 * kNumGrad];
+    __shared__ double sg[kNumLds][kAdjThreads];           // per-thread parameter gradients
     const int nx = c->nx, ny = c->ny;
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    const int tid = (int)threadIdx.x;
     const int64_t plane = (int64_t)nx * ny;
-    double gr[kNumGrad];
 #pragma unroll
-    for (int k = 0; k < kNumGrad; ++k) gr[k] = 0.0;
+    for (int k = 0; k < kNumLds; ++k) sg[k][tid] = 0.0;
 
     if (x < nx) {
         const int64_t at = (int64_t)y * nx + x;
         const double dt = c->dt, I = c->I, DI = c->DI, D = 2.0;
-        double v[NV];
-        load_dense(f, plane, at, v);
-        Blocks sb, h;
-        to_combos(v, sb);
-        forward(c->mat, sb, h);
+        Blocks h;
+        {
+            double v[NV];
+            load_dense(f, plane, at, v);
+            Blocks sb;
+            to_combos(v, sb);
+            forward(c->mat, sb, h);
+        }
         const Macro m = macro_of(h, DI);
+        const double h4 = h.ee[1];
         const double lm = lam[at];
         const double beta = al1[at];
 
@@ -300,65 +320,70 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             dly = (m.uy > 0.0 ? nnd_pos(b_m2, b_m1, lm, b_p1) : nnd_neg(b_m1, lm, b_p1, b_p2)) * c->inv_dy;
         }
 
-        Blocks e;
-        equilibrium(m.rho, m.ux, m.uy, m.T, I, e);
-
         // ---- reverse sweep --------------------------------------------------------
-        double a[NV], sbar[NV];
-        load_dense(af1, plane, at, a);
+        double sbar[NV];
+        load_dense(af1, plane, at, sbar);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) sbar[i] = dt * a[i];          // adjoint of the source term
+        for (int i = 0; i < NV; ++i) sbar[i] *= dt;                // adjoint of the source term
         double rb = 0.0, xb = 0.0, yb = 0.0, Tb = 0.0;
         double lamb = beta, dlamb = beta;
         // lambda^{n+1} = lambda + dlambda - dt (u_x D_x lambda + u_y D_y lambda)
         xb -= dt * beta * dlx;
         yb -= dt * beta * dly;
 
-        Blocks hb, eb;
+        Blocks hb;
         zero(hb);
-        zero(eb);
-
-        // src = -M^-1 g:  g_bar = -M^-T src_bar
-        Blocks gb;
-        inverse_t(c->mat, sbar, gb);
-        // g_k = R_k (h_k - e_k) - A_hat_k for k >= 5 (block slots of m1..m4 carry zero)
-        const double* R = c->R;
+        double A8b, A9b;
+        {
+            // src = -M^-1 g:  g_bar = -M^-T src_bar;  g_k = R_k (h_k - e_k) - A_hat_k, k >= 5
+            Blocks gb, e, eb;
+            inverse_t(c->mat, sbar, gb);
+            equilibrium(m.rho, m.ux, m.uy, m.T, I, e);
+            zero(eb);
+            const double* R = c->R;
 #pragma unroll
-        for (int r = 0; r < NEE; ++r) {
-            if (r < 2) continue;                                   // m1, m4
-            const double g = -gb.ee[r], d = h.ee[r] - e.ee[r];
-            gr[EE_M[r]] += g * d;
-            hb.ee[r] += R[EE_M[r]] * g;
-            eb.ee[r] -= R[EE_M[r]] * g;
+            for (int r = 2; r < NEE; ++r) {                            // skip m1, m4
+                const double g = -gb.ee[r], d = h.ee[r] - e.ee[r];
+                sg[EE_M[r] - 4][tid] = g * d;
+                hb.ee[r] = R[EE_M[r]] * g;
+                eb.ee[r] = -R[EE_M[r]] * g;
+            }
+#pragma unroll
+            for (int r = 1; r < NOE; ++r) {                            // skip m2
+                const double g = -gb.oe[r], d = h.oe[r] - e.oe[r];
+                sg[OE_M[r] - 4][tid] = g * d;
+                hb.oe[r] = R[OE_M[r]] * g;
+                eb.oe[r] = -R[OE_M[r]] * g;
+            }
+#pragma unroll
+            for (int r = 1; r < NEO; ++r) {                            // skip m3
+                const double g = -gb.eo[r], d = h.eo[r] - e.eo[r];
+                sg[EO_M[r] - 4][tid] = g * d;
+                hb.eo[r] = R[EO_M[r]] * g;
+                eb.eo[r] = -R[EO_M[r]] * g;
+            }
+#pragma unroll
+            for (int r = 0; r < NOO; ++r) {
+                const double g = -gb.oo[r], d = h.oo[r] - e.oo[r];
+                sg[OO_M[r] - 4][tid] = g * d;
+                hb.oo[r] = R[OO_M[r]] * g;
+                eb.oo[r] = -R[OO_M[r]] * g;
+            }
+            A8b = gb.oe[1];          // g_8 = ... - A_8, so A_bar_8 = -g_bar_8 = gb.oe[1]
+            A9b = gb.eo[1];
+            equilibrium_t(m.rho, m.ux, m.uy, m.T, I, eb, rb, xb, yb, Tb);
         }
+        {
+            double fb[NV];
+            forward_t(c->mat, hb, fb);                       // h_bar_1..4 are still zero here
 #pragma unroll
-        for (int r = 1; r < NOE; ++r) {                            // skip m2
-            const double g = -gb.oe[r], d = h.oe[r] - e.oe[r];
-            gr[OE_M[r]] += g * d;
-            hb.oe[r] += R[OE_M[r]] * g;
-            eb.oe[r] -= R[OE_M[r]] * g;
-        }
-#pragma unroll
-        for (int r = 1; r < NEO; ++r) {                            // skip m3
-            const double g = -gb.eo[r], d = h.eo[r] - e.eo[r];
-            gr[EO_M[r]] += g * d;
-            hb.eo[r] += R[EO_M[r]] * g;
-            eb.eo[r] -= R[EO_M[r]] * g;
-        }
-#pragma unroll
-        for (int r = 0; r < NOO; ++r) {
-            const double g = -gb.oo[r], d = h.oo[r] - e.oo[r];
-            gr[OO_M[r]] += g * d;
-            hb.oo[r] += R[OO_M[r]] * g;
-            eb.oo[r] -= R[OO_M[r]] * g;
+            for (int i = 0; i < NV; ++i) af0[i * plane + at] = fb[i];
         }
 
         // A_hat_8, A_hat_9 (Eqs. ArtificialA8/ArtificialA9), always differentiated: their
         // derivative with respect to R_8, R_9 does not vanish at R_8 = R_5, R_9 = R_7
         double GX, GY, S_b;
         {
-            const double A8b = gb.oe[1];     // g_8 = ... - A_8, g_bar_8 = -gb.oe[1]
-            const double A9b = gb.eo[1];
             const double iDI = 1.0 / DI;
             const double X8 = dux_dx - dux_dx * iDI - duy_dy * iDI;
             const double X9 = duy_dy - dux_dx * iDI - duy_dy * iDI;
@@ -378,11 +403,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             GX = X8b * (1.0 - iDI) - X9b * iDI;                 // adjoint of d u_x / dx
             GY = -X8b * iDI + X9b * (1.0 - iDI);                // adjoint of d u_y / dy
             // a8c = (R_5 - R_8)/R_5, a9c = (R_7 - R_9)/R_7
-            const double R5 = R[4], R7 = R[6], R8 = R[7], R9 = R[8];
-            gr[4] += a8cb * R8 / (R5 * R5);
-            gr[7] -= a8cb / R5;
-            gr[6] += a9cb * R9 / (R7 * R7);
-            gr[8] -= a9cb / R7;
+            const double R5 = c->R[4], R7 = c->R[6], R8 = c->R[7], R9 = c->R[8];
+            sg[0][tid] += a8cb * R8 / (R5 * R5);
+            sg[3][tid] -= a8cb / R5;
+            sg[2][tid] += a9cb * R9 / (R7 * R7);
+            sg[4][tid] -= a9cb / R7;
         }
 
         // chemistry: Cochran step and C_i
@@ -400,42 +425,42 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                 const double F = dl / dt;
                 const double kk = 1.0 / (I * DI * m.T * m.T);
                 const double K = c->Q * F * kk;
-                // f^eq = M^-1 f_hat^eq
-                Blocks se;
-                inverse(c->mat, e, se);
-                double feq[NV];
-                from_combos(se, feq);
-                double feqb[NV], Kb = 0.0, brs = 0.0, bxs = 0.0, bys = 0.0;
+                // f^eq = M^-1 f_hat^eq (f_hat^eq evaluated again here)
+                double Kb = 0.0, brs = 0.0, bxs = 0.0, bys = 0.0;
+                double* feqb = sbar;          // src_bar is not needed after this loop
+                {
+                    Blocks e, se;
+                    equilibrium(m.rho, m.ux, m.uy, m.T, I, e);
+                    inverse(c->mat, e, se);
+                    double feq[NV];
+                    from_combos(se, feq);
 #pragma unroll
-                for (int g = 0; g < 3; ++g)
+                    for (int g = 0; g < 3; ++g)
 #pragma unroll
-                    for (int d = 0; d < 8; ++d) {
-                        const int i = 8 * g + d;
-                        const double cx = c->vg[g] * DUX[d] - m.ux, cy = c->vg[g] * DUY[d] - m.uy;
-                        const double bri = -(1.0 + D) * I * m.T + I * (cx * cx + cy * cy) + c->eta2[g];
-                        feqb[i] = sbar[i] * bri * K;
-                        const double brb = sbar[i] * feq[i] * K;
-                        Kb = fma(sbar[i], feq[i] * bri, Kb);
-                        brs += brb;
-                        bxs += brb * cx;
-                        bys += brb * cy;
-                    }
+                        for (int d = 0; d < 8; ++d) {
+                            const int i = 8 * g + d;
+                            const double cx = c->vg[g] * DUX[d] - m.ux, cy = c->vg[g] * DUY[d] - m.uy;
+                            const double bri = -(1.0 + D) * I * m.T + I * (cx * cx + cy * cy) + c->eta2[g];
+                            const double sb_i = sbar[i];
+                            feqb[i] = sb_i * bri * K;
+                            const double brb = sb_i * feq[i] * K;
+                            Kb = fma(sb_i, feq[i] * bri, Kb);
+                            brs += brb;
+                            bxs += brb * cx;
+                            bys += brb * cy;
+                        }
+                }
                 Tb += -(1.0 + D) * I * brs;
                 xb += -2.0 * I * bxs;
                 yb += -2.0 * I * bys;
-                gr[24] += Kb * F * kk;                                // d/dQ
+                sg[20][tid] = Kb * F * kk;                             // d/dQ
                 const double Fb = Kb * c->Q * kk;
                 Tb += Kb * (-2.0 * K / m.T);
-                Blocks eb2;
-                inverse_t(c->mat, feqb, eb2);
-#pragma unroll
-                for (int r = 0; r < NEE; ++r) eb.ee[r] += eb2.ee[r];
-#pragma unroll
-                for (int r = 0; r < NOE; ++r) eb.oe[r] += eb2.oe[r];
-#pragma unroll
-                for (int r = 0; r < NEO; ++r) eb.eo[r] += eb2.eo[r];
-#pragma unroll
-                for (int r = 0; r < NOO; ++r) eb.oo[r] += eb2.oo[r];
+                {
+                    Blocks eb2;
+                    inverse_t(c->mat, feqb, eb2);
+                    equilibrium_t(m.rho, m.ux, m.uy, m.T, I, eb2, rb, xb, yb, Tb);
+                }
                 dlamb += Fb / dt;
                 // dl = y0 - y1(y0, cc, b)
                 const double q = cc * y0 / (den * den);
@@ -446,8 +471,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                 const double ccb = -dlamb * dy1_dcc;
                 const double bbar = -dlamb * dy1_db + ccb;
                 const double abar = ccb;
-                gr[25] += abar * pm;                                   // d/domega_1
-                gr[26] += bbar * pn;                                   // d/domega_2
+                sg[21][tid] = abar * pm;                               // d/domega_1
+                sg[22][tid] = bbar * pn;                               // d/domega_2
                 const double dpm = c->m_is_one ? 1.0 : c->pm * pow(p, c->pm - 1.0);
                 const double dpn = c->n_is_one ? 1.0 : c->pn * pow(p, c->pn - 1.0);
                 const double pb = abar * c->w1 * dpm + bbar * c->w2 * dpn;
@@ -457,22 +482,33 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             }
         }
 
-        equilibrium_t(m.rho, m.ux, m.uy, m.T, I, eb, rb, xb, yb, Tb);
-        macro_t(h, m, DI, rb, xb, yb, Tb, hb);
-        double fb[NV];
-        forward_t(c->mat, hb, fb);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) af0[i * plane + at] = a[i] + fb[i];
+        {
+            // adjoints of h_1..h_4 from those of rho, u_x, u_y, T (macro_t on zeros)
+            Blocks hh, hc;
+            zero(hc);
+            hh.ee[1] = h4;
+            macro_t(hh, m, DI, rb, xb, yb, Tb, hc);
+            Wout[3 * plane + at] = hc.ee[0];
+            Wout[4 * plane + at] = hc.oe[0];
+            Wout[5 * plane + at] = hc.eo[0];
+            Wout[6 * plane + at] = hc.ee[1];
+        }
         al0[at] = lamb;
         Wout[at] = GX;
         Wout[plane + at] = GY;
         Wout[2 * plane + at] = S_b;
     }
-    block_reduce_grad(gr, sh);
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    // fixed-order reduction of the per-thread gradients: parameter k by thread k
+    // (R_1..R_4 never receive a contribution: their moments carry g = 0)
+    if (tid < kNumGrad) {
+        double t = 0.0;
+        const int k = tid - 4;
+        if (k >= 0)
+            for (int j = 0; j < kAdjThreads; ++j) t += sg[k][j];
         const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
         const int64_t nb = (int64_t)gridDim.x * gridDim.y;
-        for (int k = 0; k < kNumGrad; ++k) part[k * nb + b] = gr[k];
+        part[tid * nb + b] = t;
     }
 }
 
@@ -492,11 +528,18 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
     const AxisAdj AX = axis_adj(x, nx, c->bc_x);
     const AxisAdj AY = axis_adj(y, ny, c->bc_y);
     int64_t ox[5], oy[5];
+    uint32_t bx[5], by[5];                 // the same as byte offsets within a plane
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
         ox[t] = row + AX.pos[t];
         oy[t] = (int64_t)AY.pos[t] * nx + x;
+        bx[t] = (uint32_t)ox[t] * 8u;
+        by[t] = (uint32_t)oy[t] * 8u;
     }
+    const uint32_t bc = (uint32_t)at * 8u;
+    // planes through buffer resources: the plane offset is a scalar operand
+    const Soa Fb = soa(f, plane), Ab = soa(af1, plane), Ob = soa(af0, plane);
+    const uint32_t pb = opaque(Fb.plane_bytes);
 
     // neighbours' A_hat terms: adjoint of this cell's velocity
     double uxn = 0.0, uyn = 0.0;
@@ -537,6 +580,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
     }
     const double rho = U[at], ux = U[plane + at], uy = U[2 * plane + at];
     const double cx_n = uxn / rho, cy_n = uyn / rho;
+    // adjoints of the conserved moments h_1..h_4 of this cell (from k_adj_local)
+    const double hb1 = W[3 * plane + at], hb2 = W[4 * plane + at], hb3 = W[5 * plane + at],
+                 hb4 = W[6 * plane + at];
 
     // transposed streaming of f: adv_i = v_ix D_x f_i + v_iy D_y f_i, adjoint -dt a_i
 #pragma unroll
@@ -545,15 +591,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const int i = 8 * g + d;
-            const double* fi = f + i * plane;
-            const double* ai = af1 + i * plane;
+            const uint32_t so = (uint32_t)i * pb;
             double acc = 0.0;
             if (DUX[d] != 0) {
                 double fv[5], av[5];
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
-                    fv[t] = fi[ox[t]];
-                    av[t] = AX.val[t] * ai[ox[t]];
+                    fv[t] = ld(Fb, so, bx[t]);
+                    av[t] = AX.val[t] * ld(Ab, so, bx[t]);
                 }
                 acc += vg * DUX[d] * c->inv_dx * nnd_t(AX, fv, av, DUX[d]);
             }
@@ -561,13 +606,15 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
                 double fv[5], av[5];
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
-                    fv[t] = fi[oy[t]];
-                    av[t] = AY.val[t] * ai[oy[t]];
+                    fv[t] = ld(Fb, so, by[t]);
+                    av[t] = AY.val[t] * ld(Ab, so, by[t]);
                 }
                 acc += vg * DUY[d] * c->inv_dy * nnd_t(AY, fv, av, DUY[d]);
             }
             const double vx = vg * DUX[d], vy = vg * DUY[d];
-            af0[i * plane + at] += -dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n;
+            const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + c->eta2[g]) * hb4;
+            const double upd = ld(Ab, so, bc) - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
+            st(Ob, so, bc, ld(Ob, so, bc) + upd);
         }
     }
 
@@ -717,12 +764,12 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_init(const Consts* __restri
 
 dim3 adj_grid(int nx, int ny) { return dim3((nx + kAdjThreads - 1) / kAdjThreads, ny); }
 
-// scratch: U (3 planes), W (3 planes), partials (27 per work-group)
+// scratch: U (3 planes), W (7 planes), partials (27 per work-group)
 lbkm_status ensure_adjoint_scratch(lbkm_ctx* ctx) {
     const int64_t cells = (int64_t)ctx->grid.nx * ctx->grid.ny;
     const dim3 g = adj_grid(ctx->grid.nx, ctx->grid.ny);
     const int64_t nb = (int64_t)g.x * g.y;
-    const int64_t need = 6 * cells + kNumGrad * nb;
+    const int64_t need = 10 * cells + kNumGrad * nb;
     if (ctx->adj_scratch && ctx->adj_scratch_n >= need) return LBKM_OK;
     if (ctx->adj_scratch) (void)hipFree(ctx->adj_scratch);
     ctx->adj_scratch = nullptr;
@@ -735,6 +782,8 @@ lbkm_status ensure_adjoint_scratch(lbkm_ctx* ctx) {
 
 lbkm_status adj_ready(lbkm_ctx* ctx) {
     if (!ctx) return LBKM_EINVAL;
+    if ((int64_t)NV * ctx->grid.nx * ctx->grid.ny * 8 > 0xFFFFFFFFll)
+        return fail(ctx, LBKM_EINVAL, "the adjoint needs a dense state below 4 GiB");
     if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
     if (!ctx->bound) return fail(ctx, LBKM_ESTATE, "buffers not bound");
     if (!ctx->params) return fail(ctx, LBKM_ESTATE, "parameters not set");
@@ -763,7 +812,7 @@ lbkm_status lbkm_adjoint_step(lbkm_ctx* ctx, const double* f_n, const double* la
     const int64_t nb = (int64_t)g.x * g.y;
     double* U = ctx->adj_scratch;
     double* W = U + 3 * cells;
-    double* part = W + 3 * cells;
+    double* part = W + 7 * cells;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_adj_macro, g, dim3(kAdjThreads), 0, s, ctx->d, f_n, U);
     hipLaunchKernelGGL(k_adj_local, g, dim3(kAdjThreads), 0, s, ctx->d, f_n, lam_n, af_np1, alam_np1, U, af_n,
@@ -793,7 +842,7 @@ lbkm_status lbkm_tne_loss(lbkm_ctx* ctx, const double* f, double* loss_dev, doub
     const int nx = ctx->grid.nx, ny = ctx->grid.ny;
     const int64_t cells = (int64_t)nx * ny;
     const dim3 g = adj_grid(nx, ny);
-    double* part = ctx->adj_scratch + 6 * cells;
+    double* part = ctx->adj_scratch + 10 * cells;
     hipLaunchKernelGGL(k_tne_loss, g, dim3(kAdjThreads), 0, ctx->stream, ctx->d, f, grad_f, part);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kAdjThreads), 0, ctx->stream, part, (int64_t)g.x * g.y, loss_dev);
     hipError_t e = hipGetLastError();
