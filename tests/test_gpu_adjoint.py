@@ -90,9 +90,10 @@ CASES = [  # nx, ny, bc_x, bc_y
     (2, 3, "periodic", "periodic"), (3, 1, "outflow", "outflow"), (5, 2, "outflow", "outflow")]
 
 
-@pytest.mark.parametrize("nx,ny,bcx,bcy", CASES)
-def test_one_adjoint_step_equals_oracle_vector_jacobian_product(nx, ny, bcx, bcy):
-    w = W.adjoint_strip(nx=nx, ny=ny).with_(bc_x=bcx, bc_y=bcy)
+@pytest.mark.parametrize("nx,ny,bcx,bcy,mn", [c + ((1.0, 1.0),) for c in CASES] +
+                         [(12, 5, "outflow", "periodic", (2.0, 0.5))])
+def test_one_adjoint_step_equals_oracle_vector_jacobian_product(nx, ny, bcx, bcy, mn):
+    w = W.adjoint_strip(nx=nx, ny=ny).with_(bc_x=bcx, bc_y=bcy, m=mn[0], n=mn[1])
     f, lam = _oracle_state(w, _random_fields(nx, ny, 100 + nx), steps=3)
     g = np.random.default_rng(7 + ny)
     af = torch.from_numpy(g.standard_normal((24, ny, nx)))

@@ -136,3 +136,27 @@ def test_full_size_batch_sampled_instances():
         d = _max_rel_diff(per[k], _single_grid(spec, k, 400))
         print("full batch vs single grid", k, spec.nx[k], f"{d:.1e}", flush=True)
         assert d <= SAME_TOL, (k, d)
+
+
+def test_batch_with_rate_exponents_and_without_modification():
+    """Two more specialisations of the persistent kernel: rate exponents m = 2, n = 0.5, and
+    a batch whose instances all have Pr = 1 (A_hat off); both against the single-grid path
+    and the shortest instance against the oracle."""
+    for tweak in ("exponents", "pr1"):
+        s = W.batched(n_inst=6, nx_lo=20, nx_hi=700, seed=23)
+        if tweak == "exponents":
+            spec = W.BatchSpec(nx=s.nx, R=s.R, Pr=s.Pr, base=s.base.with_(m=2.0, n=0.5))
+        else:
+            R = s.R.copy()
+            R[:, 7] = R[:, 4]
+            R[:, 8] = R[:, 6]
+            spec = W.BatchSpec(nx=s.nx, R=R, Pr=np.ones(len(s.nx)), base=s.base)
+        b = _lbkm().batch_from_spec(spec)
+        b.step(150)
+        b.status()
+        per = _split(b, _moments(b))
+        k0 = int(np.argmin(spec.nx))
+        _assert_parity_with_oracle(spec, k0, per[k0], 150, "batch " + tweak)
+        for k in range(len(spec.nx)):
+            d = _max_rel_diff(per[k], _single_grid(spec, k, 150))
+            assert d <= SAME_TOL, (tweak, k, d)

@@ -84,6 +84,16 @@ def test_detonation_reduced():
     assert g["lam"].max() == 1.0 and 0.0 < g["lam"][0, 200:].max() < 1.0
 
 
+def test_rate_exponents_other_than_one():
+    """The rate law with exponents m = 2, n = 0.5 (the general-exponent specialisation of
+    the kernel) and A_hat active (R_8 = 2 R_5): 600 x 3 cells, 800 steps."""
+    w = W.detonation(nx=600, ny=3, steps=800).with_(m=2.0, n=0.5, R=W.rates(100.0, r8=200.0, r9=120.0))
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    _assert_parity(g, P, tab, f, lam, label="m=2, n=0.5")
+    assert 0.0 < g["lam"][0, 200:].max() < 1.0
+
+
 @pytest.mark.parametrize("reactive", [False, True])
 def test_kh_reduced(reactive):
     """Kelvin-Helmholtz: a 96 x 128 periodic cut (rows across the lower shear layer) of the
