@@ -183,6 +183,7 @@ lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b, double* l
     ctx->h.pitch = pitch;
     ctx->h.plane = pitch * (int64_t)ctx->grid.ny;
     ctx->fields = false;
+    ctx->u_valid = false;
     lbkm_status st = ensure_device_tables(ctx);
     if (st != LBKM_OK) return st;
     ctx->bound = true;
@@ -221,6 +222,32 @@ lbkm_status lbkm_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
     if (e != hipSuccess) return hip_fail(ctx, e, "init kernel");
     ctx->fields = true;
     ctx->steps = 0;
+    ctx->u_valid = false;
+    return LBKM_OK;
+}
+
+// The velocity planes that A_hat reads: allocated on first use, computed from the current
+// state when they are not current (after init, set_state, a step without A_hat, ...).
+static lbkm_status velocity_ready(lbkm_ctx* ctx) {
+    const int64_t plane = ctx->pitch * (int64_t)ctx->grid.ny;
+    if (!ctx->u[0] || ctx->u_plane != plane) {
+        for (int i = 0; i < 2; ++i) {
+            if (ctx->u[i]) (void)hipFree(ctx->u[i]);
+            ctx->u[i] = nullptr;
+        }
+        for (int i = 0; i < 2; ++i) {
+            hipError_t e = hipMalloc((void**)&ctx->u[i], sizeof(double) * 2 * plane);
+            if (e != hipSuccess) return hip_fail(ctx, e, "allocation of the velocity planes");
+        }
+        ctx->u_plane = plane;
+        ctx->u_valid = false;
+    }
+    if (!ctx->u_valid) {
+        hipError_t e = launch_velocity(ctx->d, ctx->grid.nx, ctx->grid.ny, ctx->f[ctx->cur], ctx->u[ctx->cur],
+                                       ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "velocity kernel");
+        ctx->u_valid = true;
+    }
     return LBKM_OK;
 }
 
@@ -228,14 +255,23 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
     if (n < 0) return fail(ctx, LBKM_EINVAL, "n must be >= 0");
+    if (n == 0) return LBKM_OK;
+    const int flags = step_flags(ctx->h);
+    const bool amod = (flags & 1) != 0;
+    if (amod) {
+        st = velocity_ready(ctx);
+        if (st != LBKM_OK) return st;
+    }
     for (int64_t k = 0; k < n; ++k) {
         const int a = ctx->cur, b = 1 - a;
-        hipError_t e = launch_step(ctx->d, ctx->step_variant, step_flags(ctx->h), ctx->grid.nx, ctx->grid.ny,
-                                   ctx->f[a], ctx->f[b], ctx->lam[a], ctx->lam[b], ctx->tile_order, ctx->stream);
+        hipError_t e = launch_step(ctx->d, ctx->step_variant, flags, ctx->grid.nx, ctx->grid.ny, ctx->f[a],
+                                   ctx->f[b], ctx->lam[a], ctx->lam[b], ctx->u[a], ctx->u[b], ctx->tile_order,
+                                   ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
         ctx->cur = b;
         ++ctx->steps;
     }
+    ctx->u_valid = amod;            // a step without A_hat does not write the velocity planes
     return LBKM_OK;
 }
 
@@ -305,6 +341,7 @@ lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam) {
     if (e != hipSuccess) return hip_fail(ctx, e, "set_state");
     ctx->fields = true;
     ctx->steps = 0;
+    ctx->u_valid = false;
     return LBKM_OK;
 }
 
@@ -367,6 +404,7 @@ lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     ctx->tile_order = best_o;
     ctx->cur = cur;
     ctx->steps = steps0;
+    ctx->u_valid = false;          // the trial steps overwrote the velocity planes
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->f[cur], save, sizeof(double) * 24 * cells, hipMemcpyDeviceToDevice, ctx->stream);
     if (e == hipSuccess)
@@ -415,6 +453,8 @@ lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
     if (ctx->out8) (void)hipFree(ctx->out8);
     if (ctx->flag) (void)hipFree(ctx->flag);
     if (ctx->adj_scratch) (void)hipFree(ctx->adj_scratch);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->u[i]) (void)hipFree(ctx->u[i]);
     delete ctx;
     return LBKM_OK;
 }

@@ -54,6 +54,8 @@ struct BatchState {
     int64_t total = 0, plane = 0;
     double* f[2] = {nullptr, nullptr};
     double* lam[2] = {nullptr, nullptr};
+    double* u[2] = {nullptr, nullptr};     // velocity planes [2][plane] (inputs of A_hat)
+    bool u_valid = false;
     int cur = 0;
     std::vector<BatchInst> h_inst;
     BatchInst* d_inst = nullptr;
@@ -91,7 +93,8 @@ __device__ __forceinline__ bool wait_counter(const uint32_t* flags, int nb, int 
 // one step of one cell of a 1D instance (x-derivatives only; y-differences are zero)
 template <bool AMOD, bool CHEM, bool GEXP>
 __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const BatchInst* __restrict__ I, int lo,
-                                        int hi, int j, const Soa& F, const Soa& G, const Soa& L, const Soa& Lo) {
+                                        int hi, int j, const Soa& F, const Soa& G, const Soa& L, const Soa& Lo,
+                                        const Soa& Ui, const Soa& Uo) {
     const uint32_t oc = (uint32_t)j * 8u;
     const uint32_t om2 = (uint32_t)max(j - 2, lo) * 8u, om1 = (uint32_t)max(j - 1, lo) * 8u;
     const uint32_t op1 = (uint32_t)min(j + 1, hi) * 8u, op2 = (uint32_t)min(j + 2, hi) * 8u;
@@ -101,15 +104,10 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
     {
         double gxx = 0.0, gyx = 0.0;
         if (AMOD && I->amod) {
-            double nb[NV], ua, va, ub, vb;
-            load_cell(F, op1, nb);
-            velocity_of(c, nb, ua, va);
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, om1, nb);
-            velocity_of(c, nb, ub, vb);
-            gxx = (ua - ub) * c->half_inv_dx;
-            gyx = (va - vb) * c->half_inv_dx;
-            __builtin_amdgcn_sched_barrier(0);
+            // the neighbours' velocities, written by the previous step (or k_velocity)
+            const uint32_t up = opaque(Ui.plane_bytes);
+            gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * c->half_inv_dx;
+            gyx = (ld(Ui, up, op1) - ld(Ui, up, om1)) * c->half_inv_dx;
         }
         double f[NV];
         load_cell(F, oc, f);
@@ -125,6 +123,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
     __builtin_amdgcn_sched_barrier(0);
     const double dt = c->dt, idx_ = c->inv_dx;
     const uint32_t pb = opaque(F.plane_bytes);
+    VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const double v = c->vg[g];
@@ -135,8 +134,14 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
             double adv = 0.0;
             if (DUX[d] > 0) adv += v * (nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)) * idx_);
             if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)) * idx_);
-            st(G, so, oc, f0 + dt * (src[8 * g + d] - adv));
+            const double out = f0 + dt * (src[8 * g + d] - adv);
+            if (AMOD) vel_add(va, c, g, d, out);
+            st(G, so, oc, out);
         }
+    }
+    if (AMOD) {
+        st(Uo, 0u, oc, va.jx / va.r);
+        st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
     }
     const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, om2), ld(L, 0u, om1), lam, ld(L, 0u, op1))
                                     : nnd_neg(ld(L, 0u, om1), lam, ld(L, 0u, op1), ld(L, 0u, op2));
@@ -149,8 +154,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
                                                          const BatchSeg* __restrict__ segs,
                                                          const int32_t* __restrict__ wg_seg, int nwg,
                                                          double* f0, double* f1, double* l0, double* l1,
-                                                         int64_t steps, int parity, uint32_t* flags,
-                                                         int32_t* err) {
+                                                         double* u0, double* u1, int64_t steps, int parity,
+                                                         uint32_t* flags, int32_t* err) {
     // Ranges are dealt to the XCDs in contiguous bands (the hardware hands consecutive
     // work-group ids to the eight XCDs in turn), so neighbouring ranges, which exchange
     // halos every step, mostly share an L2.  nwg is a multiple of 8 or below 8.
@@ -162,6 +167,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
     // the loop would turn them into per-lane values)
     Soa F = soa(parity ? f1 : f0, c->plane), G = soa(parity ? f0 : f1, c->plane);
     Soa L = soa(parity ? l1 : l0, 0), Lo = soa(parity ? l0 : l1, 0);
+    Soa Ui = soa(parity ? u1 : u0, c->plane), Uo = soa(parity ? u0 : u1, c->plane);
     for (int64_t s = 0; s < steps; ++s) {
         if (s > 0) {
             if (threadIdx.x == 0) {
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
             // uniform trip count; the tail is masked
             for (int base = S.begin; base < S.end; base += kBatchThreads) {
                 const int j = base + (int)threadIdx.x;
-                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, j, F, G, L, Lo);
+                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, j, F, G, L, Lo, Ui, Uo);
             }
         }
         // The barrier orders every thread's stores before thread 0's release (cumulative),
@@ -195,6 +201,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
         t = L;
         L = Lo;
         Lo = t;
+        t = Ui;
+        Ui = Uo;
+        Uo = t;
     }
 }
 
@@ -207,8 +216,8 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 template <bool AMOD, bool CHEM, bool GEXP>
 void launch_batch_kernel(const Consts* dc, BatchState* b, int64_t steps, int parity, hipStream_t st) {
     hipLaunchKernelGGL((k_batch<AMOD, CHEM, GEXP>), dim3(b->nwg), dim3(kBatchThreads), 0, st, dc, b->d_inst,
-                       b->d_seg, b->d_wg_seg, b->nwg, b->f[0], b->f[1], b->lam[0], b->lam[1], steps, parity,
-                       b->d_flags, b->d_err);
+                       b->d_seg, b->d_wg_seg, b->nwg, b->f[0], b->f[1], b->lam[0], b->lam[1], b->u[0], b->u[1],
+                       steps, parity, b->d_flags, b->d_err);
 }
 
 const void* batch_kernel_ptr(int flags) {
@@ -314,6 +323,10 @@ lbkm_status batch_run(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
     if (n == 0) return LBKM_OK;
     const int p = b->cur;
     hipError_t e = hipSuccess;
+    if (b->any_amod && !b->u_valid) {
+        e = launch_velocity(ctx->d, (int)b->total, 1, b->f[p], b->u[p], st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "velocity kernel");
+    }
     if (!b->exec[p] || b->exec_steps[p] != n || b->exec_nwg[p] != b->nwg) {
         if (b->exec[p]) (void)hipGraphExecDestroy(b->exec[p]);
         b->exec[p] = nullptr;
@@ -334,6 +347,7 @@ lbkm_status batch_run(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
     e = hipGraphLaunch(b->exec[p], st);
     if (e != hipSuccess) return hip_fail(ctx, e, "batch graph launch");
     b->cur = (int)((p + n) & 1);
+    b->u_valid = b->any_amod;
     ctx->steps += n;
     return LBKM_OK;
 }
@@ -348,6 +362,7 @@ void destroy_extras(lbkm_ctx* ctx) {
     for (int i = 0; i < 2; ++i) {
         if (b->f[i]) (void)hipFree(b->f[i]);
         if (b->lam[i]) (void)hipFree(b->lam[i]);
+        if (b->u[i]) (void)hipFree(b->u[i]);
     }
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_seg) (void)hipFree(b->d_seg);
@@ -410,6 +425,7 @@ lbkm_status lbkm_batch_create(int32_t n_inst, const int32_t* nx, const lbkm_grid
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipMalloc((void**)&b->f[i], sizeof(double) * NV * b->plane);
         if (e == hipSuccess) e = hipMalloc((void**)&b->lam[i], sizeof(double) * b->plane);
+        if (e == hipSuccess) e = hipMalloc((void**)&b->u[i], sizeof(double) * 2 * b->plane);
     }
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_inst, sizeof(BatchInst) * n_inst);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_err, sizeof(int32_t));
@@ -456,6 +472,7 @@ lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const doubl
     if (!rho || !ux || !uy || !T || !lambda) return fail(ctx, LBKM_EINVAL, "NULL field");
     BatchState* b = ctx->batch;
     b->cur = 0;
+    b->u_valid = false;
     hipError_t e = hipMemsetAsync(b->d_err, 0, sizeof(int32_t), ctx->stream);   // a new run clears the error
     if (e == hipSuccess) e = launch_init(ctx->d, (int)b->total, 1, rho, ux, uy, T, lambda, b->f[0], b->lam[0], ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "batch init kernel");
@@ -515,6 +532,7 @@ lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg) {
     }
     if (e == hipSuccess && st == LBKM_OK) st = build_decomposition(ctx, best);
     b->cur = cur;
+    b->u_valid = false;            // the trial steps overwrote the velocity planes
     ctx->steps = steps0;
     if (e == hipSuccess) e = hipMemcpyAsync(b->f[cur], sf, sizeof(double) * NV * b->plane, hipMemcpyDeviceToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->lam[cur], sl, sizeof(double) * b->plane, hipMemcpyDeviceToDevice, ctx->stream);

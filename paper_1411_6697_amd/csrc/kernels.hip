@@ -189,6 +189,23 @@ __global__ __launch_bounds__(256) void k_check(const Consts* __restrict__ c, con
     if (bad) atomicOr(flag, 1);
 }
 
+// velocity of every cell in plane order (the same operations the step uses when it writes
+// a new state), for A_hat of the next step
+__global__ __launch_bounds__(256) void k_velocity(const Consts* __restrict__ c, const double* __restrict__ f,
+                                                  double* __restrict__ u) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= c->nx) return;
+    const int64_t at = (int64_t)y * c->pitch + x;
+    VelAcc va;
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) vel_add(va, c, g, d, f[(int64_t)(8 * g + d) * c->plane + at]);
+    u[at] = va.jx / va.r;
+    u[c->plane + at] = va.jy / va.r;
+}
+
 // pitched <-> dense copies of the state
 __global__ __launch_bounds__(256) void k_copy_state(const Consts* __restrict__ c, const double* __restrict__ src,
                                                     double* __restrict__ dst, int planes, int to_dense) {
@@ -255,6 +272,11 @@ hipError_t launch_check(const Consts* dc, int nx, int ny, const double* f, const
                         hipStream_t st) {
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, st, flag, 0);
     hipLaunchKernelGGL(k_check, row_grid(nx, ny), dim3(256), 0, st, dc, f, lam, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity(const Consts* dc, int nx, int ny, const double* f, double* u, hipStream_t st) {
+    hipLaunchKernelGGL(k_velocity, row_grid(nx, ny), dim3(256), 0, st, dc, f, u);
     return hipGetLastError();
 }
 

@@ -33,6 +33,9 @@ struct lbkm_ctx {
     double* out8 = nullptr;
     int* flag = nullptr;
     lbkm::BatchState* batch = nullptr;
+    double* u[2] = {nullptr, nullptr}; // velocity planes [2][plane] of f[0], f[1] (inputs of A_hat)
+    int64_t u_plane = 0;
+    bool u_valid = false;              // u[cur] holds the velocity of f[cur]
     double* adj_scratch = nullptr;     // adjoint step: U, W planes and parameter partials
     int64_t adj_scratch_n = 0;
     std::string err;

@@ -182,22 +182,17 @@ __device__ __forceinline__ Macro macro_of(const Blocks& h, double DI) {
     return m;
 }
 
-// rho, j_x, j_y of a cell straight from its 24 values (used for neighbour velocities)
-__device__ __forceinline__ void velocity_of(const Consts* __restrict__ c, const double f[NV],
-                                            double& ux, double& uy) {
-    double rho = 0.0, jx = 0.0, jy = 0.0;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double* q = f + 8 * g;
-        double s = 0.0;
-#pragma unroll
-        for (int d = 0; d < 8; ++d) s += q[d];
-        rho += s;
-        jx = fma(c->vg[g], (q[0] - q[2]) + (q[4] - q[5]) + (q[7] - q[6]), jx);
-        jy = fma(c->vg[g], (q[1] - q[3]) + (q[4] + q[5]) - (q[6] + q[7]), jy);
-    }
-    ux = jx / rho;
-    uy = jy / rho;
+// Velocity of a cell from its 24 values, summed plane by plane in plane order (rho, j_x,
+// j_y of Eqs. moment1-moment2).  The inputs of A_hat are the neighbours' velocities; every
+// kernel forms them with this same sequence of operations, either from stored values
+// (k_velocity) or while it writes a new state, so they agree bitwise.
+struct VelAcc {
+    double r = 0.0, jx = 0.0, jy = 0.0;
+};
+__device__ __forceinline__ void vel_add(VelAcc& a, const Consts* __restrict__ c, int g, int d, double v) {
+    a.r += v;
+    if (DUX[d] != 0) a.jx = fma(DUX[d] > 0 ? c->vg[g] : -c->vg[g], v, a.jx);
+    if (DUY[d] != 0) a.jy = fma(DUY[d] > 0 ? c->vg[g] : -c->vg[g], v, a.jy);
 }
 
 // minmod: the argument of smaller magnitude if both have the same strict sign, else 0.

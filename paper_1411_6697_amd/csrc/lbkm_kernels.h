@@ -12,8 +12,13 @@ extern const int kNumStepVariants;
 int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
 // vertical != 0: XCD-contiguous bands of tile columns (when the tile columns divide by
 // eight), else bands of tile rows
+// uin/uout: [2][plane] velocity planes of the input and output state (used and written only
+// when A_hat is active)
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
-                       double* fout, const double* lin, double* lout, int vertical, hipStream_t st);
+                       double* fout, const double* lin, double* lout, const double* uin, double* uout,
+                       int vertical, hipStream_t st);
+// velocity planes u[2][plane] of a state (pitched layout of the constants)
+hipError_t launch_velocity(const Consts* dc, int nx, int ny, const double* f, double* u, hipStream_t st);
 hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,
                        const double* uy, const double* T, const double* lam, double* f, double* lout,
                        hipStream_t st);

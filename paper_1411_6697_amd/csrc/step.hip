@@ -56,9 +56,11 @@ __device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int
 template <bool AMOD, bool CHEM, bool GEXP>
 __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Mats& M, int x, int y,
                                           const double* __restrict__ fin, double* __restrict__ fout,
-                                          const double* __restrict__ lin, double* __restrict__ lout) {
+                                          const double* __restrict__ lin, double* __restrict__ lout,
+                                          const double* __restrict__ uin, double* __restrict__ uout) {
     const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
+    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
     const Off s = stencil_offsets(c, x, y);
 
     // Phase 1: collision and chemistry from the 24 centre values -> src = -Omega + C.
@@ -68,23 +70,12 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
         // velocity gradients for A_hat first, so only four numbers are carried on
         double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
         if (AMOD) {
-            double nb[NV], ua, va, ub, vb;
-            load_cell(F, s.xp1, nb);
-            velocity_of(c, nb, ua, va);
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.xm1, nb);
-            velocity_of(c, nb, ub, vb);
-            gxx = (ua - ub) * c->half_inv_dx;          // d u_x / dx
-            gyx = (va - vb) * c->half_inv_dx;          // d u_y / dx
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.yp1, nb);
-            velocity_of(c, nb, ua, va);
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.ym1, nb);
-            velocity_of(c, nb, ub, vb);
-            gxy = (ua - ub) * c->half_inv_dy;          // d u_x / dy
-            gyy = (va - vb) * c->half_inv_dy;          // d u_y / dy
-            __builtin_amdgcn_sched_barrier(0);
+            // the four neighbours' velocities, written by the previous step (or k_velocity)
+            const uint32_t up = opaque(Ui.plane_bytes);
+            gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
+            gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
+            gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
+            gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
         }
         double f[NV];
         load_cell(F, s.c, f);
@@ -103,6 +94,7 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     // so that only src[] stays live across the planes.
     const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
     const uint32_t pb = opaque(F.plane_bytes);
+    VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const double v = c->vg[g];
@@ -115,8 +107,14 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
             if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)) * idy);
-            st_stream(G, so, s.c, f0 + dt * (src[8 * g + d] - adv));
+            const double out = f0 + dt * (src[8 * g + d] - adv);
+            if (AMOD) vel_add(va, c, g, d, out);
+            st_stream(G, so, s.c, out);
         }
+    }
+    if (AMOD) {
+        st_stream(Uo, 0u, s.c, va.jx / va.r);
+        st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
     }
     const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
                                     : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
@@ -142,6 +140,7 @@ template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
 __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, const Mats& M, int x0, int y0,
                                               const double* __restrict__ fin, double* __restrict__ fout,
                                               const double* __restrict__ lin, double* __restrict__ lout,
+                                              const double* __restrict__ uin, double* __restrict__ uout,
                                               double* __restrict__ patch /* [2][PW*PH] */) {
     using P = Patch<TX, TY>;
     const int tid = threadIdx.x;
@@ -150,6 +149,7 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     const bool inside = x < c->nx && y < c->ny;
     const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
+    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
 
     // the patch values this thread loads: LDS index and within-plane byte offset
     uint32_t goff[P::NS];
@@ -169,23 +169,12 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
         const Off s = stencil_offsets(c, x, y);
         double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
         if (AMOD) {
-            double nb[NV], ua, va, ub, vb;
-            load_cell(F, s.xp1, nb);
-            velocity_of(c, nb, ua, va);
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.xm1, nb);
-            velocity_of(c, nb, ub, vb);
-            gxx = (ua - ub) * c->half_inv_dx;
-            gyx = (va - vb) * c->half_inv_dx;
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.yp1, nb);
-            velocity_of(c, nb, ua, va);
-            __builtin_amdgcn_sched_barrier(0);
-            load_cell(F, s.ym1, nb);
-            velocity_of(c, nb, ub, vb);
-            gxy = (ua - ub) * c->half_inv_dy;
-            gyy = (va - vb) * c->half_inv_dy;
-            __builtin_amdgcn_sched_barrier(0);
+            // the four neighbours' velocities, written by the previous step (or k_velocity)
+            const uint32_t up = opaque(Ui.plane_bytes);
+            gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
+            gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
+            gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
+            gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
         }
         double f[NV];
         load_cell(F, s.c, f);
@@ -209,6 +198,7 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     const uint32_t out_off = ((uint32_t)y * (uint32_t)c->pitch + (uint32_t)x) * 8u;
     const int cidx = (ly + 2) * P::PW + (lx + 2);
     double pre[P::NS];
+    VelAcc va;                                  // velocity of the new state (for A_hat)
     auto fetch = [&](int plane) {
 #pragma unroll
         for (int j = 0; j < P::NS; ++j) {
@@ -235,8 +225,14 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
             if (DUX[d] < 0) adv -= v * (nnd_neg(q[-1], f0, q[1], q[2]) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]) * idy);
-            if (inside) st_stream(G, (uint32_t)i * pb, out_off, f0 + dt * (src[i] - adv));
+            const double out = f0 + dt * (src[i] - adv);
+            if (AMOD) vel_add(va, c, g, d, out);
+            if (inside) st_stream(G, (uint32_t)i * pb, out_off, out);
         } else if (inside) {
+            if (AMOD) {
+                st_stream(Uo, 0u, out_off, va.jx / va.r);
+                st_stream(Uo, opaque(Uo.plane_bytes), out_off, va.jy / va.r);
+            }
             const double dlx = (m.ux > 0.0) ? nnd_pos(q[-2], q[-1], f0, q[1]) : nnd_neg(q[-1], f0, q[1], q[2]);
             const double dly = (m.uy > 0.0) ? nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW])
                                             : nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
@@ -268,51 +264,54 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
 __global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
-                                                  double* __restrict__ lout, int gx, int ntiles, int vertical) {
+                                                  double* __restrict__ lout, const double* __restrict__ uin,
+                                                  double* __restrict__ uout, int gx, int ntiles, int vertical) {
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c->nx || y >= c->ny) return;
-    step_cell<AMOD, CHEM, GEXP>(c, c->mat, x, y, fin, fout, lin, lout);
+    step_cell<AMOD, CHEM, GEXP>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout);
 }
 
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
 __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__ c,
                                                       const double* __restrict__ fin, double* __restrict__ fout,
                                                       const double* __restrict__ lin, double* __restrict__ lout,
+                                                      const double* __restrict__ uin, double* __restrict__ uout,
                                                       int gx, int ntiles, int vertical) {
     __shared__ double patch[2 * Patch<TX, TY>::N];
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
-    step_tile_lds<TX, TY, AMOD, CHEM, GEXP>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, patch);
+    step_tile_lds<TX, TY, AMOD, CHEM, GEXP>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, uin, uout, patch);
 }
 
 template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
-                        double* lout, int vertical, hipStream_t st) {
+                        double* lout, const double* uin, double* uout, int vertical, hipStream_t st) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
     if (LDS)
         hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
-                           fin, fout, lin, lout, gx, ntiles, vertical);
+                           fin, fout, lin, lout, uin, uout, gx, ntiles, vertical);
     else
         hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
-                           fout, lin, lout, gx, ntiles, vertical);
+                           fout, lin, lout, uin, uout, gx, ntiles, vertical);
     return hipGetLastError();
 }
 
 template <int TX, int TY, bool LDS>
 hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
-                        const double* lin, double* lout, int vertical, hipStream_t st) {
+                        const double* lin, double* lout, const double* uin, double* uout, int vertical,
+                        hipStream_t st) {
     switch (flags) {
-        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
-        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
     }
 }
 
@@ -329,14 +328,15 @@ int step_flags(const Consts& c) {
 }
 
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
-                       double* fout, const double* lin, double* lout, int vertical, hipStream_t st) {
+                       double* fout, const double* lin, double* lout, const double* uin, double* uout,
+                       int vertical, hipStream_t st) {
     switch (variant) {
-        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
-        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
-        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, vertical, st);
+        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
     }
 }
 
