@@ -439,7 +439,7 @@ lbkm_status lbkm_get_step_count(lbkm_ctx* ctx, int64_t* out) {
 }
 
 lbkm_status lbkm_copy_kernel(const double* src, double* dst, int64_t n, void* hip_stream) {
-    if (!src || !dst || n < 0) return LBKM_EINVAL;
+    if (!src || !dst || n < 0 || (n / 2 + 255) / 256 > INT32_MAX) return LBKM_EINVAL;
     return launch_copy(src, dst, n, (hipStream_t)hip_stream) == hipSuccess ? LBKM_OK : LBKM_EDEVICE;
 }
 

@@ -224,15 +224,11 @@ __global__ __launch_bounds__(256) void k_copy_state(const Consts* __restrict__ c
 
 __global__ void k_fill_int(int* p, int v) { *p = v; }
 
-// plain streaming copy (bandwidth calibration): 16-byte accesses, four per thread
+// plain streaming copy (bandwidth calibration): one 16-byte access per thread
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst,
                                               int64_t n2) {
-    const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t i = base + 256 * k;
-        if (i < n2) dst[i] = src[i];
-    }
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n2) dst[i] = src[i];
 }
 
 }  // namespace
@@ -289,7 +285,7 @@ hipError_t launch_copy_state(const Consts* dc, int nx, int ny, const double* src
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
     const int64_t n2 = n / 2;
     if (n2 > 0)
-        hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 1023) / 1024)), dim3(256), 0, st, (const double2*)src,
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, (const double2*)src,
                            (double2*)dst, n2);
     if (n & 1) (void)hipMemcpyAsync(dst + n - 1, src + n - 1, sizeof(double), hipMemcpyDeviceToDevice, st);
     return hipGetLastError();

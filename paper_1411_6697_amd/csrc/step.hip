@@ -261,8 +261,11 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
     return true;
 }
 
+// At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
+// general: the reactive specialisations then fit without spilling and the compiler stops
+// parking scalar registers in vector lanes; the general-exponent ones would spill.
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
-__global__ __launch_bounds__(TX * TY) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
+__global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
                                                   double* __restrict__ lout, const double* __restrict__ uin,
                                                   double* __restrict__ uout, int gx, int ntiles, int vertical) {
