@@ -220,7 +220,7 @@ def bench_adjoint(ns_per_cell_plain):
     torch.cuda.synchronize()
     ms_adj = e0.elapsed_time(e1) / reps
     return {"workload": f"detonation_strip_{w.nx}x{w.ny}_{w.steps}_steps_checkpoint_50",
-            "loss": float(loss), "gradient_wall_s": round(times[-1], 4),
+            "loss": float(loss.detach()), "gradient_wall_s": round(times[-1], 4),
             "plain_step_ms": round(ms_plain, 5), "adjoint_step_ms": round(ms_adj, 5),
             "adjoint_step_vs_plain_step": round(ms_adj / ms_plain, 3),
             "gradient_vs_plain_run": round(times[-1] / (w.steps * ms_plain * 1e-3), 3),
