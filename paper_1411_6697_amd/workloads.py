@@ -130,6 +130,38 @@ def sod(nx: int = 400, ny: int = 1, steps: int = 2000, paper_rates: bool = False
                                     lambda w: 0.5 * w.nx * w.dx))
 
 
+# Velocity models of the Lax and Sjogren runs (Sec. IV B 2 and 3).
+DVM_LAX = (4.7, 3.3, 1.0, 6.0, 2.5, 0.9)
+DVM_SJOGREN = (0.4, 1.0, 1.8, 0.3, 1.9, 1.5)
+
+
+def lax(nx: int = 2000, ny: int = 1, steps: int = 15000) -> Workload:
+    """Lax shock tube (Sec. IV B 2): (rho, T, u_x, u_y) = (0.445, 7.928, 0.698, 0) on [-1, 0)
+    and (0.5, 1.142, 0, 0) on [0, 1]; dx = dy = 1e-3, dt = 1e-5, I = 1 (gamma = 5/3),
+    DVM (4.7, 3.3, 1, 6, 2.5, 0.9), R_5..R_7 = 2e4, R_8 = R_9 = 8e4 (Pr = 4, A_hat active),
+    other R_k = 1e5; t = 0.15 after 15000 steps.  The domain is cell-centred on
+    [0, nx dx] with the interface at its middle."""
+    R = rates(1e5, r5=2e4, r6=2e4, r7=2e4, r8=8e4, r9=8e4)
+    return Workload(
+        name="lax", nx=nx, ny=ny, dx=1e-3, dy=1e-3, dt=1e-5, steps=steps, dvm=DVM_LAX,
+        gamma=5.0 / 3.0, I=1.0, R=R, bc_x=OUTFLOW, bc_y=PERIODIC,
+        make_fields=_riemann_fields((0.445, 0.698, 0.0, 7.928), (0.5, 0.0, 0.0, 1.142),
+                                    lambda w: 0.5 * w.nx * w.dx))
+
+
+def sjogren(nx: int = 500, ny: int = 1, steps: int = 1500) -> Workload:
+    """Sjogren's problem (Sec. IV B 3), two receding streams: (rho, T, u_x, u_y) =
+    (1, 0.5, -1.2, 0) on [-0.5, 0) and (1, 0.5, 1.2, 0) on [0, 0.5]; dx = dy = 2e-3,
+    dt = 2e-5, I = 4 (gamma = 4/3), DVM (0.4, 1.0, 1.8, 0.3, 1.9, 1.5), R_8 = R_9 = 2e4,
+    other R_k = 5e4 (Pr = 0.4, A_hat active); t = 0.03 after 1500 steps."""
+    R = rates(5e4, r8=2e4, r9=2e4)
+    return Workload(
+        name="sjogren", nx=nx, ny=ny, dx=2e-3, dy=2e-3, dt=2e-5, steps=steps, dvm=DVM_SJOGREN,
+        gamma=4.0 / 3.0, I=4.0, R=R, bc_x=OUTFLOW, bc_y=PERIODIC,
+        make_fields=_riemann_fields((1.0, -1.2, 0.0, 0.5), (1.0, 1.2, 0.0, 0.5),
+                                    lambda w: 0.5 * w.nx * w.dx))
+
+
 # --------------------------------------------------------------------------
 # Detonation
 # --------------------------------------------------------------------------
