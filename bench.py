@@ -7,10 +7,12 @@ chemistry and C_i, M^-1, NND streaming, forward Euler, lambda update), i.e. one 
 the fused step kernel.  Reported beside it on the same GPU: the batched form (128 ragged
 1D detonations, one persistent launch per graph replay) and the adjoint form (gradient of
 the non-equilibrium loss over a 2048 x 256 detonation strip, 500 steps, checkpoints every
-50), each against the plain step's time per cell-update.  Prints one JSON line.
+50), each against the plain step's time per cell-update, and the reactive run with the
+single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I).  Prints one
+JSON line.
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
-                  [--no-inert] [--no-batched] [--no-adjoint]
+                  [--no-inert] [--no-batched] [--no-adjoint] [--no-srt]
 """
 
 from __future__ import annotations
@@ -238,6 +240,7 @@ def main():
     ap.add_argument("--no-inert", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-srt", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -269,6 +272,19 @@ def main():
         torch.cuda.empty_cache()
         inert = {"mlups": round(cells / (ms0 * 1e-3) / 1e6, 2), "ms_per_step": round(ms0, 5)}
 
+    srt = None
+    if not args.no_srt:
+        # the same reactive run with the single-relaxation-time collision (Eq. SRT), tau = 1/R_k
+        ws = w.with_(tau=1.0 / w.R[4])
+        s1 = lbkm.sim_from_workload(ws)
+        launch_srt = s1.autotune()
+        ms1 = time_steps(s1, args.steps, args.warmup)
+        del s1
+        torch.cuda.empty_cache()
+        srt = {"tau": ws.tau, "mlups": round(cells / (ms1 * 1e-3) / 1e6, 2), "ms_per_step": round(ms1, 5),
+               "launch": list(launch_srt), "mrt_over_srt_time": round(ms / ms1, 4),
+               "paper_table_I_mrt_over_srt_time": round(2293.93 / 2221.58, 4)}
+
     achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
     ceiling = copy_ceiling_gbs()
     traffic = measured_traffic()
@@ -295,6 +311,7 @@ def main():
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL,
                      "copy_kernel_gbs": round(ceiling, 1)},
         "inert_Q0": inert,
+        "srt_collision": srt,
     }
     ns_cell = ms * 1e6 / cells
     if not args.no_batched:

@@ -149,6 +149,17 @@ lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t
  * vertical = 0 (the default) a band of tile rows.  Results do not depend on it. */
 lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical);
 
+/* Collision form of the single-grid step (Sec. V, Eq. SRT).  tau > 0: the
+ * single-relaxation-time form, -(f_i - M^-1_il f_hat^eq_l) / tau + C_i, with one
+ * relaxation time tau for all 24 distribution functions and no modification term
+ * (R_1..R_24 and Pr of lbkm_set_params are then unused).  tau = 0 (the state after
+ * lbkm_create): the multiple-relaxation-time form of Eq. Boltzmann_chemical.  Errors:
+ * EINVAL if tau < 0, not finite, or dt / tau >= 2 (forward Euler relaxation unstable);
+ * ESTATE on a batched context.  lbkm_adjoint_step refuses a context in the SRT form
+ * (ESTATE).  Takes effect from the next step (the constants are uploaded, and the stream
+ * waited for, once buffers and parameters are set). */
+lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau);
+
 /* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
  * orders for a few steps from the current state, keeps the fastest, and restores the
  * state and the step count (the trial steps run on the bound buffers; a temporary copy

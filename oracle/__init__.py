@@ -32,6 +32,9 @@ the mathematics, never against the oracle itself):
   collision             mass, momentum and energy conservation; closed-form decay
                         (1 - R_k dt)^n of every non-conserved moment (pins forward
                         Euler and the R-to-moment mapping)
+  collision_srt         one SRT step with tau equals one MRT step with every R_k =
+                        1/tau (A_hat then vanishes; an identity of Eqs. SRT and MRT);
+                        closed-form decay (1 - dt/tau)^n of every component of f - f^eq
   modification_terms    its sign: only the chosen sign makes the viscous heating
                         independent of R_8 (Chapman-Enskog, Sec. III)
   cochran_increment     exact solution of the rate equation (against a fine RK4);
@@ -41,7 +44,8 @@ the mathematics, never against the oracle itself):
                         parity unpinned (the paper prints no value for them)
   nnd_derivative,       exact on linear data, zero on constants, upwind, second
   streaming             order on smooth monotone data, mirror symmetry
-  step, run, init_f     Sod against the exact Riemann solution; the CJ plateau of a
+  step, run, init_f     Sod (I = 3), Lax (I = 1) and Sjogren (I = 4) against the exact
+                        Riemann solutions; the CJ plateau of a
                         detonation; shear-wave decay at the Chapman-Enskog
                         viscosity; conservation on periodic grids
   tne, reductions       readout identities (Sec. VI)
@@ -57,7 +61,7 @@ printed; a project choice of the workloads).
 from .dvm import DVM, velocity_set, moment_matrix, inverse_moment_matrix
 from .model import Params, Tables, make_tables, equilibrium_moments, macroscopic, \
     modification_terms, cochran_increment, chemical_term, nnd_derivative, \
-    collision, step, run, init_f, moments, tne, reductions
+    collision, collision_srt, step, run, init_f, moments, tne, reductions
 
 __all__ = [
     "DVM", "velocity_set", "moment_matrix", "inverse_moment_matrix",

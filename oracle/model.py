@@ -67,6 +67,7 @@ class Params:
     T_ig: float = 1.1             # ignition temperature
     bc_x: str = OUTFLOW
     bc_y: str = PERIODIC
+    tau: float = 0.0              # > 0: single-relaxation-time collision of Eq. SRT (Sec. V)
 
 
 @dataclass
@@ -244,6 +245,12 @@ def collision(fhat, feq_hat, A8, A9, tab: Tables):
     return torch.einsum("il,l...->i...", tab.Minv, g)
 
 
+def collision_srt(f, feq, tau: float):
+    """Omega_i = (f_i - M^-1_il f_hat^eq_l) / tau (Eq. SRT): one relaxation time for all
+    24 distribution functions, towards the discrete equilibrium; no A_hat."""
+    return (f - feq) / tau
+
+
 def cochran_increment(lam, p, T, P: Params, tab: Tables):
     """Reaction increment of lambda over one step (Eq. lambda_equation, Cochran rate,
     temporal part solved analytically with p frozen).
@@ -278,8 +285,8 @@ def chemical_term(feq, ux, uy, T, F, P: Params, tab: Tables):
 # --------------------------------------------------------------------------
 
 def step(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
-    """One forward-Euler step of Eq. Boltzmann_chemical for f and of
-    Eq. lambda_equation for lambda, every term evaluated at level n.
+    """One forward-Euler step of Eq. Boltzmann_chemical (or, with P.tau > 0, of Eq. SRT)
+    for f and of Eq. lambda_equation for lambda, every term evaluated at level n.
 
     f^{n+1} = f^n + dt [ -v_i.grad_NND f_i - Omega_i + C_i ]
     lambda^{n+1} = lambda^n + dlambda_chem - dt u.grad_NND lambda
@@ -288,12 +295,15 @@ def step(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
     rho, ux, uy, T = macroscopic(fhat, P.I)
     p = rho * T
     feq_hat = equilibrium_moments(rho, ux, uy, T, P.I)
-    A8, A9 = modification_terms(rho, ux, uy, T, P, tab)
-    omega = collision(fhat, feq_hat, A8, A9, tab)
+    feq = torch.einsum("ik,k...->i...", tab.Minv, feq_hat)
+    if P.tau > 0:
+        omega = collision_srt(f, feq, P.tau)
+    else:
+        A8, A9 = modification_terms(rho, ux, uy, T, P, tab)
+        omega = collision(fhat, feq_hat, A8, A9, tab)
 
     dlam = cochran_increment(lam, p, T, P, tab)
     F = dlam / P.dt
-    feq = torch.einsum("ik,k...->i...", tab.Minv, feq_hat)
     C = chemical_term(feq, ux, uy, T, F, P, tab)
 
     adv = streaming(f, P, tab)

@@ -355,6 +355,18 @@ lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t
     return fail(ctx, LBKM_EINVAL, "unsupported step tile shape");
 }
 
+lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
+    if (!std::isfinite(tau) || tau < 0.0) return fail(ctx, LBKM_EINVAL, "tau must be finite and >= 0");
+    if (tau > 0.0 && !(ctx->grid.dt / tau < 2.0))
+        return fail(ctx, LBKM_EINVAL, "dt / tau >= 2: forward Euler relaxation is unstable");
+    ctx->h.srt = tau > 0.0 ? 1 : 0;
+    ctx->h.inv_tau = tau > 0.0 ? 1.0 / tau : 0.0;
+    ctx->u_valid = false;
+    return ctx->bound && ctx->params ? upload_consts(ctx) : LBKM_OK;
+}
+
 lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
     if (!ctx) return LBKM_EINVAL;
     if (vertical != 0 && vertical != 1) return fail(ctx, LBKM_EINVAL, "vertical must be 0 or 1");

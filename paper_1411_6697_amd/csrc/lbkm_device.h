@@ -238,6 +238,24 @@ __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double l
     return y0 - y1;
 }
 
+// C_i = f^eq_i Q [-(1+D) I T + I |v_i - u|^2 + eta_i^2] F / (I (D+I) T^2) with F = dlam/dt
+// (Eq. C_i, discrete f^eq), added to src.
+__device__ __forceinline__ void add_chemical(const Consts* __restrict__ c, const Macro& m, double dlam,
+                                             const double feq[NV], double src[NV]) {
+    const double F = dlam / c->dt;
+    const double common = c->Q * F / (c->I * c->DI * m.T * m.T);
+    const double base = -(1.0 + 2.0) * c->I * m.T;
+#pragma unroll
+    for (int g2 = 0; g2 < 3; ++g2)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const double cx = c->vg[g2] * DUX[d] - m.ux;
+            const double cy = c->vg[g2] * DUY[d] - m.uy;
+            const double br = base + c->I * (cx * cx + cy * cy) + c->eta2[g2];
+            src[8 * g2 + d] += feq[8 * g2 + d] * (common * br);
+        }
+}
+
 // Collision and chemistry of one cell.
 // Input: the macroscopic state m, the moments h = M f of the cell, lam, A8/A9 (modification
 // terms, 0 if inactive).  Output: src[i] = -Omega_i + C_i (the non-streaming right-hand
@@ -278,7 +296,6 @@ __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const
     }
     dlam = cochran<CHEM, GEXP>(c, lam, m.rho * m.T, m.T);
     if (CHEM && dlam != 0.0) {
-        // C_i = f^eq_i Q [-(1+D) I T + I |v_i - u|^2 + eta_i^2] F / (I (D+I) T^2), F = dlam/dt.
         // f_hat^eq is evaluated again (from an opaque copy of T, so the compiler does not
         // reuse the first evaluation) rather than kept live through the collision.
         __builtin_amdgcn_sched_barrier(0);
@@ -290,19 +307,49 @@ __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const
         inverse(M, e2, se);
         double feq[NV];
         from_combos(se, feq);
-        const double F = dlam / c->dt;
-        const double common = c->Q * F / (c->I * c->DI * m.T * m.T);
-        const double base = -(1.0 + 2.0) * c->I * m.T;
-#pragma unroll
-        for (int g2 = 0; g2 < 3; ++g2)
-#pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                const double cx = c->vg[g2] * DUX[d] - m.ux;
-                const double cy = c->vg[g2] * DUY[d] - m.uy;
-                const double br = base + c->I * (cx * cx + cy * cy) + c->eta2[g2];
-                src[8 * g2 + d] += feq[8 * g2 + d] * (common * br);
-            }
+        add_chemical(c, m, dlam, feq, src);
     }
+}
+
+// rho, u and T from the conserved sums of Eqs. moment1-moment3 taken straight over the 24
+// values (rho = sum f, j = sum f v, sum f (v^2 + eta^2) = rho ((D+I) T + u^2)).
+__device__ __forceinline__ Macro macro_sums(const Consts* __restrict__ c, const double f[NV]) {
+    double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double v = c->vg[g];
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const double x = f[8 * g + d];
+            r += x;
+            if (DUX[d] != 0) jx = fma(DUX[d] > 0 ? v : -v, x, jx);
+            if (DUY[d] != 0) jy = fma(DUY[d] > 0 ? v : -v, x, jy);
+            e = fma((double)(DUX[d] * DUX[d] + DUY[d] * DUY[d]) * (v * v) + c->eta2[g], x, e);
+        }
+    }
+    Macro m;
+    m.rho = r;
+    m.ux = jx / r;
+    m.uy = jy / r;
+    m.T = (e / r - m.ux * m.ux - m.uy * m.uy) / c->DI;
+    return m;
+}
+
+// Single-relaxation-time source (Eq. SRT): src_i = -(f_i - f^eq_i) / tau + C_i with the
+// discrete equilibrium f^eq = M^-1 f_hat^eq, which also serves C_i.  No A_hat.
+template <bool CHEM = true, bool GEXP = true>
+__device__ __forceinline__ void srt_source(const Consts* __restrict__ c, const Mats& M, double lam,
+                                           const Macro& m, const double f[NV], double src[NV],
+                                           double& dlam) {
+    Blocks e, se;
+    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+    inverse(M, e, se);
+    double feq[NV];
+    from_combos(se, feq);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) src[i] = (feq[i] - f[i]) * c->inv_tau;
+    dlam = cochran<CHEM, GEXP>(c, lam, m.rho * m.T, m.T);
+    if (CHEM && dlam != 0.0) add_chemical(c, m, dlam, feq, src);
 }
 
 // A_hat_8, A_hat_9 (Eqs. ArtificialA8/ArtificialA9) from central differences of u

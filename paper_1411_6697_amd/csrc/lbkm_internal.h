@@ -38,6 +38,8 @@ struct Consts {
     double Q, w1, w2, pm, pn, Tig;
     double dt, inv_dx, inv_dy, half_inv_dx, half_inv_dy;
     double a8c, a9c;              // (R_5 - R_8)/R_5 and (R_7 - R_9)/R_7
+    double inv_tau;               // 1/tau of the single-relaxation-time form
+    int32_t srt;                  // 1: single relaxation time (Eq. SRT) instead of MRT
     int32_t amod;                 // 1 if A_hat_8 or A_hat_9 can be non-zero
     int32_t chem;                 // 1 if the reaction can run (omega1 or omega2 > 0)
     int32_t m_is_one, n_is_one;   // exponents equal to 1 (p^1 = p exactly)

@@ -51,9 +51,46 @@ __device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int
     return s;
 }
 
+// Phase 1 of one cell: src = -Omega + C (the right-hand side without streaming), the
+// reaction increment dlam, lambda and the macroscopic state, from the cell's 24 values at
+// level n (and, when A_hat is active, the four neighbours' velocities, written by the
+// previous step or by k_velocity).  SRT: the single-relaxation-time form of Eq. SRT.
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
+__device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const Mats& M, const Soa& F,
+                                            const Soa& L, const Soa& Ui, const Off& s, double src[NV],
+                                            double& dlam, double& lam, Macro& m) {
+    double f[NV];
+    if (SRT) {
+        load_cell(F, s.c, f);
+        m = macro_sums(c, f);
+        lam = ld(L, 0u, s.c);
+        srt_source<CHEM, GEXP>(c, M, lam, m, f, src, dlam);
+        return;
+    }
+    // velocity gradients for A_hat first, so only four numbers are carried on
+    double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
+    if (AMOD) {
+        const uint32_t up = opaque(Ui.plane_bytes);
+        gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
+        gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
+        gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
+        gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
+    }
+    load_cell(F, s.c, f);
+    Blocks sb, h;
+    to_combos(f, sb);
+    forward(M, sb, h);
+    m = macro_of(h, c->DI);
+    double A8 = 0.0, A9 = 0.0;
+    if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
+    lam = ld(L, 0u, s.c);
+    local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
+}
+
 // one full time step of one cell (all inputs at level n); M holds the matrix blocks.
-// AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1.
-template <bool AMOD, bool CHEM, bool GEXP>
+// AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1;
+// SRT: single relaxation time (then AMOD is false).
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
 __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Mats& M, int x, int y,
                                           const double* __restrict__ fin, double* __restrict__ fout,
                                           const double* __restrict__ lin, double* __restrict__ lout,
@@ -66,28 +103,7 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     // Phase 1: collision and chemistry from the 24 centre values -> src = -Omega + C.
     double src[NV], dlam, lam;
     Macro m;
-    {
-        // velocity gradients for A_hat first, so only four numbers are carried on
-        double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
-        if (AMOD) {
-            // the four neighbours' velocities, written by the previous step (or k_velocity)
-            const uint32_t up = opaque(Ui.plane_bytes);
-            gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
-            gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
-            gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
-            gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
-        }
-        double f[NV];
-        load_cell(F, s.c, f);
-        Blocks sb, h;
-        to_combos(f, sb);
-        forward(M, sb, h);
-        m = macro_of(h, c->DI);
-        double A8 = 0.0, A9 = 0.0;
-        if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
-        lam = ld(L, 0u, s.c);
-        local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
-    }
+    cell_source<AMOD, CHEM, GEXP, SRT>(c, M, F, L, Ui, s, src, dlam, lam, m);
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 2: NND streaming plane by plane; the centre value is read again (a cache hit)
@@ -136,7 +152,7 @@ struct Patch {
     static constexpr int NS = (N + NT - 1) / NT;     // patch values loaded per thread
 };
 
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
 __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, const Mats& M, int x0, int y0,
                                               const double* __restrict__ fin, double* __restrict__ fout,
                                               const double* __restrict__ lin, double* __restrict__ lout,
@@ -167,25 +183,7 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     Macro m{1.0, 0.0, 0.0, 1.0};
     if (inside) {
         const Off s = stencil_offsets(c, x, y);
-        double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
-        if (AMOD) {
-            // the four neighbours' velocities, written by the previous step (or k_velocity)
-            const uint32_t up = opaque(Ui.plane_bytes);
-            gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
-            gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
-            gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
-            gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
-        }
-        double f[NV];
-        load_cell(F, s.c, f);
-        Blocks sb, h;
-        to_combos(f, sb);
-        forward(M, sb, h);
-        m = macro_of(h, c->DI);
-        double A8 = 0.0, A9 = 0.0;
-        if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
-        lam = ld(L, 0u, s.c);
-        local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
+        cell_source<AMOD, CHEM, GEXP, SRT>(c, M, F, L, Ui, s, src, dlam, lam, m);
     } else {
 #pragma unroll
         for (int i = 0; i < NV; ++i) src[i] = 0.0;
@@ -264,7 +262,7 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
 // general: the reactive specialisations then fit without spilling and the compiler stops
 // parking scalar registers in vector lanes; the general-exponent ones would spill.
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
 __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
                                                   double* __restrict__ lout, const double* __restrict__ uin,
@@ -274,10 +272,10 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step(const Consts* __
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c->nx || y >= c->ny) return;
-    step_cell<AMOD, CHEM, GEXP>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout);
+    step_cell<AMOD, CHEM, GEXP, SRT>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout);
 }
 
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
 __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__ c,
                                                       const double* __restrict__ fin, double* __restrict__ fout,
                                                       const double* __restrict__ lin, double* __restrict__ lout,
@@ -286,20 +284,20 @@ __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__
     __shared__ double patch[2 * Patch<TX, TY>::N];
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
-    step_tile_lds<TX, TY, AMOD, CHEM, GEXP>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, uin, uout, patch);
+    step_tile_lds<TX, TY, AMOD, CHEM, GEXP, SRT>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, uin, uout, patch);
 }
 
-template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP>
+template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP, bool SRT>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
                         double* lout, const double* uin, double* uout, int vertical, hipStream_t st) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
     if (LDS)
-        hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
+        hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP, SRT>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
                            fin, fout, lin, lout, uin, uout, gx, ntiles, vertical);
     else
-        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
+        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
                            fout, lin, lout, uin, uout, gx, ntiles, vertical);
     return hipGetLastError();
 }
@@ -309,12 +307,16 @@ hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const doubl
                         const double* lin, double* lout, const double* uin, double* uout, int vertical,
                         hipStream_t st) {
     switch (flags) {
-        case 0: return launch_tiles<TX, TY, LDS, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 1: return launch_tiles<TX, TY, LDS, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 2: return launch_tiles<TX, TY, LDS, false, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 3: return launch_tiles<TX, TY, LDS, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 6: return launch_tiles<TX, TY, LDS, false, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        default: return launch_tiles<TX, TY, LDS, true, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 0: return launch_tiles<TX, TY, LDS, false, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 1: return launch_tiles<TX, TY, LDS, true, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 2: return launch_tiles<TX, TY, LDS, false, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 3: return launch_tiles<TX, TY, LDS, true, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 6: return launch_tiles<TX, TY, LDS, false, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 7: return launch_tiles<TX, TY, LDS, true, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 8: return launch_tiles<TX, TY, LDS, false, false, false, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 10: return launch_tiles<TX, TY, LDS, false, true, false, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 14: return launch_tiles<TX, TY, LDS, false, true, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -327,7 +329,9 @@ const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 
 int step_flags(const Consts& c) {
     const bool chem = c.chem != 0;
-    return (c.amod ? 1 : 0) | (chem ? 2 : 0) | ((chem && !(c.m_is_one && c.n_is_one)) ? 4 : 0);
+    const int rest = (chem ? 2 : 0) | ((chem && !(c.m_is_one && c.n_is_one)) ? 4 : 0);
+    if (c.srt) return 8 | rest;                   // no A_hat in the single-relaxation-time form
+    return (c.amod ? 1 : 0) | rest;
 }
 
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,

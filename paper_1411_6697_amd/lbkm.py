@@ -66,6 +66,7 @@ SIGNATURES = {
     "lbkm_get_matrices": [_P, _D, _D, _D],
     "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "lbkm_set_tile_order": [_P, ctypes.c_int32],
+    "lbkm_set_srt": [_P, ctypes.c_double],
     "lbkm_autotune": [_P, ctypes.POINTER(ctypes.c_int32)],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -233,6 +234,10 @@ class Sim:
 
     def set_tile_order(self, vertical: int):
         self._call("lbkm_set_tile_order", ctypes.c_int32(int(vertical)))
+
+    def set_srt(self, tau: float):
+        """tau > 0: single-relaxation-time collision (Eq. SRT); tau = 0: MRT (the default)."""
+        self._call("lbkm_set_srt", ctypes.c_double(float(tau)))
 
     def autotune(self):
         """Pick the fastest launch shape on this device; returns (tile_x, tile_y, lds, vertical)."""
@@ -434,6 +439,8 @@ def sim_from_workload(w, device="cuda:0", pitch=None, fields=None) -> Sim:
     paper_1411_6697_amd.workloads (input generation only)."""
     s = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.dvm, w.bc_x, w.bc_y, device=device, pitch=pitch)
     s.set_params(w.R, w.gamma, 0.0, w.Q, w.omega1, w.omega2, w.m, w.n, w.T_ig)
+    if getattr(w, "tau", 0.0) > 0.0:
+        s.set_srt(w.tau)
     F = fields if fields is not None else w.fields()
     s.init_fields(F["rho"], F["ux"], F["uy"], F["T"], F["lam"])
     return s

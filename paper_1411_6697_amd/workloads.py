@@ -56,6 +56,7 @@ class Workload:
     T_ig: float = 1.1
     bc_x: str = OUTFLOW
     bc_y: str = PERIODIC
+    tau: float = 0.0                  # > 0: single-relaxation-time collision (Sec. V)
     make_fields: Optional[Callable[["Workload"], Dict[str, np.ndarray]]] = field(default=None, repr=False)
     meta: dict = field(default_factory=dict)
 

@@ -91,6 +91,19 @@ def test_set_params_validates(kw, status):
         _destroy(h)
 
 
+@pytest.mark.parametrize("tau,status", [(1e-4, 0), (0.0, 0), (-1e-4, -1), (float("nan"), -1),
+                                        (float("inf"), -1), (1e-5 / 2.5, -1), (1e-5 / 1.9, 0)])
+def test_set_srt_validates(tau, status):
+    """Single-relaxation-time switch (Eq. SRT): tau >= 0, finite, dt / tau < 2."""
+    st, h, msg = _create(_grid())
+    assert st == 0, msg
+    try:
+        st = L.load().lbkm_set_srt(h, tau)
+        assert st == status, L.load().lbkm_last_error(h).decode()
+    finally:
+        _destroy(h)
+
+
 def test_calls_out_of_order_are_rejected():
     lib = L.load()
     st, h, msg = _create(_grid())
@@ -103,7 +116,8 @@ def test_calls_out_of_order_are_rejected():
         _destroy(h)
 
 
-@pytest.mark.parametrize("d", [W.DVM_SOD, W.DVM_STEADY_DET, W.DVM_UNSTEADY_DET, (0.8, 1.2, 1.3, 1.0, 2.7, 0.8)])
+@pytest.mark.parametrize("d", [W.DVM_SOD, W.DVM_STEADY_DET, W.DVM_UNSTEADY_DET, (0.8, 1.2, 1.3, 1.0, 2.7, 0.8),
+                               W.DVM_LAX, W.DVM_SJOGREN])
 def test_library_moment_matrix_matches_oracle(d):
     """The library's M equals the oracle's correctly rounded M entry by entry, and its
     block inverse agrees with the oracle's exactly rounded M^-1 to a few ulp of the

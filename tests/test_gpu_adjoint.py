@@ -119,6 +119,24 @@ def test_one_adjoint_step_equals_oracle_vector_jacobian_product(nx, ny, bcx, bcy
     _param_close(grad.cpu().numpy(), ref_theta, 1e-9, label + " d/dtheta")
 
 
+def test_adjoint_step_refuses_the_srt_form():
+    """The adjoint covers the MRT form of Eq. Boltzmann_chemical only: a context switched to
+    the single-relaxation-time form refuses an adjoint step (ESTATE), and accepts it again
+    once switched back."""
+    w = W.adjoint_strip(nx=8, ny=3)
+    f, lam = _oracle_state(w, _random_fields(8, 3, 11), steps=1)
+    s = _sim(w)
+    dev = s.device
+    args = (f.to(dev).contiguous(), lam.to(dev).contiguous(), torch.ones(24, 3, 8, dtype=torch.float64, device=dev),
+            torch.ones(3, 8, dtype=torch.float64, device=dev))
+    s.set_srt(1e-2)
+    with pytest.raises(_lbkm().LbkmError, match="MRT"):
+        s.adjoint_step(*args, torch.zeros(NG, dtype=torch.float64, device=dev))
+    s.set_srt(0.0)
+    s.adjoint_step(*args, torch.zeros(NG, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+
+
 def test_tne_loss_and_its_gradient_match_oracle():
     w = W.adjoint_strip(nx=24, ny=5)
     f, lam = _oracle_state(w, _random_fields(24, 5, 3), steps=4)

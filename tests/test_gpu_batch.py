@@ -89,6 +89,17 @@ def test_ragged_edge_batch_matches_oracle_per_instance():
         _assert_parity_with_oracle(spec, k, per[k], 300, "edge batch")
 
 
+def test_batch_refuses_the_srt_switch():
+    """The single-relaxation-time form is a single-grid option; a batched context refuses
+    it (ESTATE) and keeps stepping in the MRT form."""
+    L = _lbkm()
+    b = L.batch_from_spec(_edge_spec())
+    assert b.lib.lbkm_set_srt(b.h, 1e-3) == -5
+    assert "batched" in b.lib.lbkm_last_error(b.h).decode()
+    b.step(2)
+    b.status()
+
+
 def test_batch_agrees_with_single_grid_path():
     spec = _edge_spec()
     b = _lbkm().batch_from_spec(spec)

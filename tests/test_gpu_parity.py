@@ -150,6 +150,29 @@ def test_kh_reduced(reactive):
     _assert_parity(g, P, tab, f, lam, label=f"kh-cut reactive={reactive}")
 
 
+@pytest.mark.parametrize("case", ["sod", "detonation", "kh-cut"])
+def test_srt_collision_matches_oracle(case):
+    """The single-relaxation-time form (Eq. SRT, lbkm_set_srt) with tau = 1/R of each
+    configuration: Sod 400 x 1 (2000 steps), the detonation on 600 x 3 cells (600 steps,
+    reaction and C_i from the same discrete equilibrium) and the 96 x 128 KH cut (reactive,
+    150 steps)."""
+    F = None
+    if case == "sod":
+        w = W.sod().with_(tau=1.0 / 1.2e4)
+    elif case == "detonation":
+        w = W.detonation(nx=600, ny=3, steps=600).with_(tau=1.0 / 100.0)
+    else:
+        w = W.kh(n=2048, steps=150, reactive=True)
+        F = {k: np.ascontiguousarray(v[448:576, 1000:1096]) for k, v in w.fields().items()}
+        w = w.with_(nx=96, ny=128, tau=1.0 / 2e4)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    assert P.tau == w.tau > 0
+    _assert_parity(g, P, tab, f, lam, label=f"srt {case}")
+    if case == "detonation":
+        assert 0.0 < g["lam"][0, 200:].max() < 1.0
+
+
 def _window_oracle(w, fields, cells, K):
     """Advance the oracle K steps on a (4K+1)^2 window around each cell (periodic wrap in
     x and y) and return the centre cell's moments."""
@@ -248,8 +271,9 @@ VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 
 @pytest.mark.parametrize("w", [W.detonation(nx=333, ny=7, steps=30).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
                                                                          bc_y="outflow"),
                                W.kh(n=2048, steps=30).with_(nx=130, ny=67),
-                               W.kh(n=2048, steps=20).with_(nx=2040, ny=9)],
-                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9"])
+                               W.kh(n=2048, steps=20).with_(nx=2040, ny=9),
+                               W.kh(n=2048, steps=30).with_(nx=130, ny=67, tau=1.0 / 2e4)],
+                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67"])
 def test_launch_variants_give_bitwise_identical_results(w):
     """Every compiled launch shape (LDS-staged or not) in both tile orders computes the same
     bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the

@@ -164,6 +164,49 @@ def test_relaxation_closed_form_pins_euler_and_rate_indices():
     assert not torch.allclose(got, rk2, rtol=1e-3)
 
 
+def test_srt_step_equals_mrt_step_with_equal_rates():
+    """Eq. SRT against Eq. MRT (Sec. V): with every R_k = 1/tau, M^-1 R (f_hat - f_hat^eq)
+    = (f - M^-1 f_hat^eq)/tau and A_hat vanishes (R_8 = R_5, R_9 = R_7), so one SRT step
+    equals one MRT step.  Random O(1) fields on a periodic 8 x 5 grid with the reaction
+    running in every cell (C_i included); an SRT step with another tau must differ."""
+    tau = 1.0 / 3e3
+    g = np.random.default_rng(5)
+    F = dict(rho=1.0 + 0.2 * g.random((5, 8)), ux=0.1 * g.standard_normal((5, 8)),
+             uy=0.1 * g.standard_normal((5, 8)), T=1.25 + 0.3 * g.random((5, 8)),
+             lam=0.2 + 0.5 * g.random((5, 8)))
+    w = W.detonation(nx=8, ny=5, steps=3).with_(bc_x="periodic", bc_y="periodic", T_ig=1.0)
+    mrt = oracle_run(w.with_(R=tuple([1.0 / tau] * 24)), fields=F)
+    srt = oracle_run(w.with_(tau=tau), fields=F)
+    assert float((mrt[3] - 1.0).abs().max()) > 1e-3          # reaction ran
+    scale = float(mrt[2].abs().max())
+    assert float((srt[2] - mrt[2]).abs().max()) < 1e-13 * scale
+    assert torch.equal(srt[3], mrt[3]) or float((srt[3] - mrt[3]).abs().max()) < 1e-14
+    other = oracle_run(w.with_(tau=1.1 * tau), fields=F)
+    assert float((other[2] - mrt[2]).abs().max()) > 1e-8 * scale
+
+
+def test_srt_relaxation_closed_form():
+    """Eq. SRT for a uniform state with f = f^eq + delta (delta carrying no mass, momentum or
+    energy) and no reaction: every one of the 24 components of f - f^eq decays as
+    (1 - dt/tau)^n under forward Euler, and rho, u, T stay put."""
+    tau = 1.0 / 7e3
+    P = _params(R=W.rates(1e4), dt=2e-5, bc_x="periodic", bc_y="periodic", tau=tau)
+    tab = om.make_tables(P)
+    t = lambda v: torch.full((2, 3), v, dtype=T64)
+    feq_hat = om.equilibrium_moments(t(1.1), t(0.2), t(-0.1), t(1.3), P.I)
+    feq = torch.einsum("ik,k...->i...", tab.Minv, feq_hat)
+    dhat = torch.zeros(24, dtype=T64)
+    dhat[4:] = 1e-3 * torch.linspace(-1.0, 1.0, 20, dtype=T64) * feq_hat[4:, 0, 0].abs()
+    delta = tab.Minv @ dhat
+    f = feq + delta.reshape(-1, 1, 1)
+    n = 9
+    f, lam = om.run(f, torch.zeros(2, 3, dtype=T64), P, tab, n)
+    m = om.moments(f, lam, P, tab)
+    assert abs(float(m["rho"][0, 0]) - 1.1) < 1e-13 and abs(float(m["T"][0, 0]) - 1.3) < 1e-13
+    want = (1.0 - P.dt / tau) ** n * delta
+    assert torch.allclose((f - feq)[:, 0, 0], want, rtol=1e-9, atol=1e-12 * float(delta.abs().max()))
+
+
 def _delta8_in_compressive_wave(R8, flip_sign=False):
     nx = 64
     x = (np.arange(nx) + 0.5) / nx
