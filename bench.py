@@ -8,11 +8,11 @@ the fused step kernel.  Reported beside it on the same GPU: the batched form (12
 1D detonations, one persistent launch per graph replay) and the adjoint form (gradient of
 the non-equilibrium loss over a 2048 x 256 detonation strip, 500 steps, checkpoints every
 50), each against the plain step's time per cell-update, and the reactive run with the
-single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I).  Prints one
-JSON line.
+single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I) and with the
+SSP Runge-Kutta time schemes.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
-                  [--no-inert] [--no-batched] [--no-adjoint] [--no-srt]
+                  [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk]
 """
 
 from __future__ import annotations
@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-srt", action="store_true")
+    ap.add_argument("--no-rk", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -285,6 +286,20 @@ def main():
                "launch": list(launch_srt), "mrt_over_srt_time": round(ms / ms1, 4),
                "paper_table_I_mrt_over_srt_time": round(2293.93 / 2221.58, 4)}
 
+    schemes = None
+    if not args.no_rk:
+        # the same reactive run with the SSP Runge-Kutta schemes (2 and 3 stage launches per step)
+        schemes = {}
+        for rk in (2, 3):
+            s2 = lbkm.sim_from_workload(w.with_(rk=rk))
+            s2.set_tile(*launch[:3])
+            s2.set_tile_order(launch[3])
+            ms2 = time_steps(s2, max(args.steps // rk, 1), args.warmup)
+            schemes[f"rk{rk}"] = {"ms_per_step": round(ms2, 5), "mlups": round(cells / (ms2 * 1e-3) / 1e6, 2),
+                                  "time_over_euler": round(ms2 / ms, 4), "finite": bool(s2.check())}
+            del s2
+            torch.cuda.empty_cache()
+
     achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
     ceiling = copy_ceiling_gbs()
     traffic = measured_traffic()
@@ -312,6 +327,7 @@ def main():
                      "copy_kernel_gbs": round(ceiling, 1)},
         "inert_Q0": inert,
         "srt_collision": srt,
+        "runge_kutta": schemes,
     }
     ns_cell = ms * 1e6 / cells
     if not args.no_batched:

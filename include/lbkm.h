@@ -160,6 +160,19 @@ lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical);
  * waited for, once buffers and parameters are set). */
 lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau);
 
+/* Time integration of the single-grid step.  order = 1: forward Euler (the default, the
+ * reading of Eq. Boltzmann_chemical's time derivative used throughout); order = 2: the
+ * two-stage and order = 3: the three-stage strong-stability-preserving Runge-Kutta schemes
+ * of Shu and Osher (1988), whose stages are forward-Euler updates of the whole right-hand
+ * side (streaming, collision, C_i, and the lambda equation with its Cochran increment as
+ * the rate times dt) combined with f^n:
+ *   RK2: g1 = E(f^n);  f^{n+1} = f^n/2 + E(g1)/2
+ *   RK3: g1 = E(f^n);  g2 = 3/4 f^n + 1/4 E(g1);  f^{n+1} = 1/3 f^n + 2/3 E(g2).
+ * One lbkm_step advances one full step (2 or 3 kernel launches).  RK3 allocates a third
+ * state (library-owned, freed by lbkm_destroy).  Errors: EINVAL for another order; ESTATE on
+ * a batched context.  lbkm_adjoint_step refuses order != 1 (ESTATE). */
+lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order);
+
 /* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
  * orders for a few steps from the current state, keeps the fastest, and restores the
  * state and the step count (the trial steps run on the bound buffers; a temporary copy

@@ -68,6 +68,7 @@ class Params:
     bc_x: str = OUTFLOW
     bc_y: str = PERIODIC
     tau: float = 0.0              # > 0: single-relaxation-time collision of Eq. SRT (Sec. V)
+    rk: int = 1                   # time scheme: 1 forward Euler, 2 / 3 SSP Runge-Kutta
 
 
 @dataclass
@@ -284,7 +285,7 @@ def chemical_term(feq, ux, uy, T, F, P: Params, tab: Tables):
 # The time step
 # --------------------------------------------------------------------------
 
-def step(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
+def euler_update(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
     """One forward-Euler step of Eq. Boltzmann_chemical (or, with P.tau > 0, of Eq. SRT)
     for f and of Eq. lambda_equation for lambda, every term evaluated at level n.
 
@@ -315,6 +316,26 @@ def step(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
                       nnd_derivative(lam, 0, False, P.bc_y, P.dy))
     lam_new = lam + dlam - P.dt * (ux * dlx + uy * dly)
     return f_new, lam_new
+
+
+def step(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
+    """One time step.  P.rk = 1: forward Euler (euler_update).  P.rk = 2, 3: the strong-
+    stability-preserving Runge-Kutta schemes of Shu and Osher (1988) written as convex
+    combinations of forward-Euler updates E of the whole right-hand side (the reaction
+    increment over dt standing for dt times the rate):
+        RK2: g1 = E(f);  f' = f/2 + E(g1)/2
+        RK3: g1 = E(f);  g2 = 3/4 f + 1/4 E(g1);  f' = 1/3 f + 2/3 E(g2)
+    and the same combinations for lambda."""
+    if P.rk == 1:
+        return euler_update(f, lam, P, tab)
+    g1, l1 = euler_update(f, lam, P, tab)
+    e1, m1 = euler_update(g1, l1, P, tab)
+    if P.rk == 2:
+        return 0.5 * f + 0.5 * e1, 0.5 * lam + 0.5 * m1
+    g2, l2 = 0.75 * f + 0.25 * e1, 0.75 * lam + 0.25 * m1
+    e2, m2 = euler_update(g2, l2, P, tab)
+    a, b = 1.0 / 3.0, 2.0 / 3.0
+    return a * f + b * e2, a * lam + b * m2
 
 
 def run(f, lam, P: Params, tab: Tables, nsteps: int):

@@ -251,6 +251,27 @@ static lbkm_status velocity_ready(lbkm_ctx* ctx) {
     return LBKM_OK;
 }
 
+// The third state of SSP-RK3 (f, lambda and, with A_hat, velocity planes), library-owned.
+static lbkm_status rk3_ready(lbkm_ctx* ctx, bool amod) {
+    const int64_t plane = ctx->pitch * (int64_t)ctx->grid.ny;
+    if (ctx->rk3_plane != plane) {
+        for (double** p : {&ctx->f3, &ctx->lam3, &ctx->u3}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        ctx->rk3_plane = 0;
+        hipError_t e = hipMalloc((void**)&ctx->f3, sizeof(double) * NV * plane);
+        if (e == hipSuccess) e = hipMalloc((void**)&ctx->lam3, sizeof(double) * plane);
+        if (e != hipSuccess) return hip_fail(ctx, e, "allocation of the third Runge-Kutta state");
+        ctx->rk3_plane = plane;
+    }
+    if (amod && !ctx->u3) {
+        hipError_t e = hipMalloc((void**)&ctx->u3, sizeof(double) * 2 * plane);
+        if (e != hipSuccess) return hip_fail(ctx, e, "allocation of the third Runge-Kutta state");
+    }
+    return LBKM_OK;
+}
+
 lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
@@ -262,13 +283,33 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
         st = velocity_ready(ctx);
         if (st != LBKM_OK) return st;
     }
+    if (ctx->rk == 3) {
+        st = rk3_ready(ctx, amod);
+        if (st != LBKM_OK) return st;
+    }
+    const int nx = ctx->grid.nx, ny = ctx->grid.ny, var = ctx->step_variant, ord = ctx->tile_order;
     for (int64_t k = 0; k < n; ++k) {
         const int a = ctx->cur, b = 1 - a;
-        hipError_t e = launch_step(ctx->d, ctx->step_variant, flags, ctx->grid.nx, ctx->grid.ny, ctx->f[a],
-                                   ctx->f[b], ctx->lam[a], ctx->lam[b], ctx->u[a], ctx->u[b], ctx->tile_order,
-                                   ctx->stream);
+        double *fa = ctx->f[a], *fb = ctx->f[b], *la = ctx->lam[a], *lb = ctx->lam[b];
+        double *ua = ctx->u[a], *ub = ctx->u[b];
+        // forward Euler, and the first stage of both Runge-Kutta schemes: state b = E(state a)
+        hipError_t e = launch_step(ctx->d, var, flags, nx, ny, fa, fb, la, lb, ua, ub, ord, ctx->stream);
+        if (e == hipSuccess && ctx->rk == 2) {
+            // f^{n+1} = f^n / 2 + E(g_1) / 2, written over f^n
+            const Blend bl{nullptr, nullptr, 0.5, 0.5};
+            e = launch_step(ctx->d, var, flags, nx, ny, fb, fa, lb, la, ub, ua, ord, ctx->stream, &bl);
+        } else if (e == hipSuccess && ctx->rk == 3) {
+            // g_2 = 3/4 f^n + 1/4 E(g_1); f^{n+1} = 1/3 f^n + 2/3 E(g_2), written over f^n
+            const Blend b2{fa, la, 0.75, 0.25};
+            e = launch_step(ctx->d, var, flags, nx, ny, fb, ctx->f3, lb, ctx->lam3, ub, ctx->u3, ord, ctx->stream,
+                            &b2);
+            const Blend b3{nullptr, nullptr, 1.0 / 3.0, 2.0 / 3.0};
+            if (e == hipSuccess)
+                e = launch_step(ctx->d, var, flags, nx, ny, ctx->f3, fa, ctx->lam3, la, ctx->u3, ua, ord,
+                                ctx->stream, &b3);
+        }
         if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
-        ctx->cur = b;
+        if (ctx->rk == 1) ctx->cur = b;
         ++ctx->steps;
     }
     ctx->u_valid = amod;            // a step without A_hat does not write the velocity planes
@@ -365,6 +406,14 @@ lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau) {
     ctx->h.inv_tau = tau > 0.0 ? 1.0 / tau : 0.0;
     ctx->u_valid = false;
     return ctx->bound && ctx->params ? upload_consts(ctx) : LBKM_OK;
+}
+
+lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
+    if (order < 1 || order > 3) return fail(ctx, LBKM_EINVAL, "order must be 1, 2 or 3");
+    ctx->rk = order;
+    return LBKM_OK;
 }
 
 lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
@@ -467,6 +516,8 @@ lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
     if (ctx->adj_scratch) (void)hipFree(ctx->adj_scratch);
     for (int i = 0; i < 2; ++i)
         if (ctx->u[i]) (void)hipFree(ctx->u[i]);
+    for (double* p : {ctx->f3, ctx->lam3, ctx->u3})
+        if (p) (void)hipFree(p);
     delete ctx;
     return LBKM_OK;
 }

@@ -36,6 +36,11 @@ struct lbkm_ctx {
     double* u[2] = {nullptr, nullptr}; // velocity planes [2][plane] of f[0], f[1] (inputs of A_hat)
     int64_t u_plane = 0;
     bool u_valid = false;              // u[cur] holds the velocity of f[cur]
+    int rk = 1;                        // time scheme: 1 forward Euler, 2 SSP-RK2, 3 SSP-RK3
+    double* f3 = nullptr;              // third state for SSP-RK3 (library-owned): f, lambda, u
+    double* lam3 = nullptr;
+    double* u3 = nullptr;
+    int64_t rk3_plane = 0;
     double* adj_scratch = nullptr;     // adjoint step: U, W planes and parameter partials
     int64_t adj_scratch_n = 0;
     std::string err;

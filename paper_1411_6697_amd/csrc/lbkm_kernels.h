@@ -14,9 +14,19 @@ int step_flags(const Consts& c);        // compile-time specialisation of the st
 // eight), else bands of tile rows
 // uin/uout: [2][plane] velocity planes of the input and output state (used and written only
 // when A_hat is active)
+// Stage of a Runge-Kutta step: the output is a * (f^n, lambda^n at the cell) + b * (the
+// forward-Euler update of the input state).  fn, ln = nullptr: f^n and lambda^n are the
+// output buffers themselves (the stage writes over them; each thread reads its own cell
+// before writing it); otherwise they must not overlap the output.
+struct Blend {
+    const double* fn;
+    const double* ln;
+    double a, b;
+};
+// bl == nullptr: a plain forward-Euler step
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
-                       int vertical, hipStream_t st);
+                       int vertical, hipStream_t st, const Blend* bl = nullptr);
 // velocity planes u[2][plane] of a state (pitched layout of the constants)
 hipError_t launch_velocity(const Consts* dc, int nx, int ny, const double* f, double* u, hipStream_t st);
 hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,

@@ -89,15 +89,20 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
 
 // one full time step of one cell (all inputs at level n); M holds the matrix blocks.
 // AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1;
-// SRT: single relaxation time (then AMOD is false).
-template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
+// SRT: single relaxation time (then AMOD is false); BLEND: a Runge-Kutta stage, the result
+// is bl.a * (f^n, lambda^n) + bl.b * (the forward-Euler update).
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
 __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Mats& M, int x, int y,
                                           const double* __restrict__ fin, double* __restrict__ fout,
                                           const double* __restrict__ lin, double* __restrict__ lout,
-                                          const double* __restrict__ uin, double* __restrict__ uout) {
+                                          const double* __restrict__ uin, double* __restrict__ uout,
+                                          const Blend& bl) {
     const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
     const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
+    // f^n, lambda^n of a Runge-Kutta stage; null: the output buffers themselves (in place)
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
+    const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
     const Off s = stencil_offsets(c, x, y);
 
     // Phase 1: collision and chemistry from the 24 centre values -> src = -Omega + C.
@@ -123,7 +128,8 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
             if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)) * idy);
-            const double out = f0 + dt * (src[8 * g + d] - adv);
+            double out = f0 + dt * (src[8 * g + d] - adv);
+            if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
             if (AMOD) vel_add(va, c, g, d, out);
             st_stream(G, so, s.c, out);
         }
@@ -136,7 +142,9 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
                                     : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
     const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
                                     : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
-    st_stream(Lo, 0u, s.c, lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+    double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+    if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
+    st_stream(Lo, 0u, s.c, lnew);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -152,12 +160,12 @@ struct Patch {
     static constexpr int NS = (N + NT - 1) / NT;     // patch values loaded per thread
 };
 
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
 __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, const Mats& M, int x0, int y0,
-                                              const double* __restrict__ fin, double* __restrict__ fout,
-                                              const double* __restrict__ lin, double* __restrict__ lout,
+                                              const double* __restrict__ fin, double* fout,
+                                              const double* __restrict__ lin, double* lout,
                                               const double* __restrict__ uin, double* __restrict__ uout,
-                                              double* __restrict__ patch /* [2][PW*PH] */) {
+                                              const Blend& bl, double* __restrict__ patch /* [2][PW*PH] */) {
     using P = Patch<TX, TY>;
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
@@ -166,6 +174,8 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
     const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
+    const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
 
     // the patch values this thread loads: LDS index and within-plane byte offset
     uint32_t goff[P::NS];
@@ -223,7 +233,8 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
             if (DUX[d] < 0) adv -= v * (nnd_neg(q[-1], f0, q[1], q[2]) * idx_);
             if (DUY[d] > 0) adv += v * (nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]) * idy);
             if (DUY[d] < 0) adv -= v * (nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]) * idy);
-            const double out = f0 + dt * (src[i] - adv);
+            double out = f0 + dt * (src[i] - adv);
+            if (BLEND && inside) out = fma(bl.a, ld(Fn, (uint32_t)i * pb, out_off), bl.b * out);
             if (AMOD) vel_add(va, c, g, d, out);
             if (inside) st_stream(G, (uint32_t)i * pb, out_off, out);
         } else if (inside) {
@@ -234,7 +245,9 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
             const double dlx = (m.ux > 0.0) ? nnd_pos(q[-2], q[-1], f0, q[1]) : nnd_neg(q[-1], f0, q[1], q[2]);
             const double dly = (m.uy > 0.0) ? nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW])
                                             : nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
-            st_stream(Lo, 0u, out_off, f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy)));
+            double lnew = f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+            if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, out_off), bl.b * lnew);
+            st_stream(Lo, 0u, out_off, lnew);
         }
     }
 }
@@ -262,62 +275,77 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
 // general: the reactive specialisations then fit without spilling and the compiler stops
 // parking scalar registers in vector lanes; the general-exponent ones would spill.
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
 __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
                                                   double* __restrict__ lout, const double* __restrict__ uin,
-                                                  double* __restrict__ uout, int gx, int ntiles, int vertical) {
+                                                  double* __restrict__ uout, int gx, int ntiles, int vertical,
+                                                  Blend bl) {
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c->nx || y >= c->ny) return;
-    step_cell<AMOD, CHEM, GEXP, SRT>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout);
+    step_cell<AMOD, CHEM, GEXP, SRT, BLEND>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout, bl);
 }
 
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
 __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__ c,
-                                                      const double* __restrict__ fin, double* __restrict__ fout,
-                                                      const double* __restrict__ lin, double* __restrict__ lout,
+                                                      const double* __restrict__ fin, double* fout,
+                                                      const double* __restrict__ lin, double* lout,
                                                       const double* __restrict__ uin, double* __restrict__ uout,
-                                                      int gx, int ntiles, int vertical) {
+                                                      int gx, int ntiles, int vertical, Blend bl) {
     __shared__ double patch[2 * Patch<TX, TY>::N];
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
-    step_tile_lds<TX, TY, AMOD, CHEM, GEXP, SRT>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, uin, uout, patch);
+    step_tile_lds<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>(c, c->mat, tx * TX, ty * TY, fin, fout, lin, lout, uin, uout,
+                                                        bl, patch);
 }
 
-template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
-                        double* lout, const double* uin, double* uout, int vertical, hipStream_t st) {
+                        double* lout, const double* uin, double* uout, int vertical, hipStream_t st,
+                        const Blend& bl) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
     if (LDS)
-        hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP, SRT>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
-                           fin, fout, lin, lout, uin, uout, gx, ntiles, vertical);
+        hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
+                           st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
     else
-        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc, fin,
-                           fout, lin, lout, uin, uout, gx, ntiles, vertical);
+        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
+                           fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
     return hipGetLastError();
 }
 
-template <int TX, int TY, bool LDS>
+template <int TX, int TY, bool LDS, bool BLEND>
 hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
                         const double* lin, double* lout, const double* uin, double* uout, int vertical,
-                        hipStream_t st) {
+                        hipStream_t st, const Blend& bl) {
+#define LBKM_TILES(A, C, G, S) \
+    launch_tiles<TX, TY, LDS, A, C, G, S, BLEND>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl)
     switch (flags) {
-        case 0: return launch_tiles<TX, TY, LDS, false, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 1: return launch_tiles<TX, TY, LDS, true, false, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 2: return launch_tiles<TX, TY, LDS, false, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 3: return launch_tiles<TX, TY, LDS, true, true, false, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 6: return launch_tiles<TX, TY, LDS, false, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 7: return launch_tiles<TX, TY, LDS, true, true, true, false>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 8: return launch_tiles<TX, TY, LDS, false, false, false, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 10: return launch_tiles<TX, TY, LDS, false, true, false, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 14: return launch_tiles<TX, TY, LDS, false, true, true, true>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 0: return LBKM_TILES(false, false, false, false);
+        case 1: return LBKM_TILES(true, false, false, false);
+        case 2: return LBKM_TILES(false, true, false, false);
+        case 3: return LBKM_TILES(true, true, false, false);
+        case 6: return LBKM_TILES(false, true, true, false);
+        case 7: return LBKM_TILES(true, true, true, false);
+        case 8: return LBKM_TILES(false, false, false, true);
+        case 10: return LBKM_TILES(false, true, false, true);
+        case 14: return LBKM_TILES(false, true, true, true);
         default: return hipErrorInvalidValue;
     }
+#undef LBKM_TILES
+}
+
+template <int TX, int TY, bool LDS>
+hipError_t launch_shape(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
+                        const double* lin, double* lout, const double* uin, double* uout, int vertical,
+                        hipStream_t st, const Blend* bl) {
+    if (bl) return launch_flags<TX, TY, LDS, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, *bl);
+    const Blend none{nullptr, nullptr, 0.0, 1.0};
+    return launch_flags<TX, TY, LDS, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, none);
 }
 
 }  // namespace
@@ -336,14 +364,14 @@ int step_flags(const Consts& c) {
 
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
-                       int vertical, hipStream_t st) {
+                       int vertical, hipStream_t st, const Blend* bl) {
     switch (variant) {
-        case 1: return launch_flags<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 2: return launch_flags<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 3: return launch_flags<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 4: return launch_flags<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        case 5: return launch_flags<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
-        default: return launch_flags<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st);
+        case 1: return launch_shape<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 2: return launch_shape<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 3: return launch_shape<256, 2, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 4: return launch_shape<256, 1, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 5: return launch_shape<64, 4, false>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        default: return launch_shape<64, 4, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
     }
 }
 

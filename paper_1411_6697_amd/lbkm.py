@@ -67,6 +67,7 @@ SIGNATURES = {
     "lbkm_set_tile": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "lbkm_set_tile_order": [_P, ctypes.c_int32],
     "lbkm_set_srt": [_P, ctypes.c_double],
+    "lbkm_set_time_scheme": [_P, ctypes.c_int32],
     "lbkm_autotune": [_P, ctypes.POINTER(ctypes.c_int32)],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -234,6 +235,10 @@ class Sim:
 
     def set_tile_order(self, vertical: int):
         self._call("lbkm_set_tile_order", ctypes.c_int32(int(vertical)))
+
+    def set_time_scheme(self, order: int):
+        """1: forward Euler (default); 2, 3: SSP Runge-Kutta of that order."""
+        self._call("lbkm_set_time_scheme", ctypes.c_int32(int(order)))
 
     def set_srt(self, tau: float):
         """tau > 0: single-relaxation-time collision (Eq. SRT); tau = 0: MRT (the default)."""
@@ -441,6 +446,8 @@ def sim_from_workload(w, device="cuda:0", pitch=None, fields=None) -> Sim:
     s.set_params(w.R, w.gamma, 0.0, w.Q, w.omega1, w.omega2, w.m, w.n, w.T_ig)
     if getattr(w, "tau", 0.0) > 0.0:
         s.set_srt(w.tau)
+    if getattr(w, "rk", 1) != 1:
+        s.set_time_scheme(w.rk)
     F = fields if fields is not None else w.fields()
     s.init_fields(F["rho"], F["ux"], F["uy"], F["T"], F["lam"])
     return s

@@ -57,6 +57,7 @@ class Workload:
     bc_x: str = OUTFLOW
     bc_y: str = PERIODIC
     tau: float = 0.0                  # > 0: single-relaxation-time collision (Sec. V)
+    rk: int = 1                       # time scheme: 1 forward Euler, 2/3 SSP Runge-Kutta
     make_fields: Optional[Callable[["Workload"], Dict[str, np.ndarray]]] = field(default=None, repr=False)
     meta: dict = field(default_factory=dict)
 

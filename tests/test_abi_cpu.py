@@ -104,6 +104,17 @@ def test_set_srt_validates(tau, status):
         _destroy(h)
 
 
+@pytest.mark.parametrize("order,status", [(1, 0), (2, 0), (3, 0), (0, -1), (4, -1), (-2, -1)])
+def test_set_time_scheme_validates(order, status):
+    """Forward Euler (1) or the SSP Runge-Kutta schemes of order 2 and 3."""
+    st, h, msg = _create(_grid())
+    assert st == 0, msg
+    try:
+        assert L.load().lbkm_set_time_scheme(h, order) == status
+    finally:
+        _destroy(h)
+
+
 def test_calls_out_of_order_are_rejected():
     lib = L.load()
     st, h, msg = _create(_grid())

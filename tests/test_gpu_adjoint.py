@@ -119,10 +119,10 @@ def test_one_adjoint_step_equals_oracle_vector_jacobian_product(nx, ny, bcx, bcy
     _param_close(grad.cpu().numpy(), ref_theta, 1e-9, label + " d/dtheta")
 
 
-def test_adjoint_step_refuses_the_srt_form():
-    """The adjoint covers the MRT form of Eq. Boltzmann_chemical only: a context switched to
-    the single-relaxation-time form refuses an adjoint step (ESTATE), and accepts it again
-    once switched back."""
+def test_adjoint_step_refuses_srt_and_runge_kutta():
+    """The adjoint covers the MRT form of Eq. Boltzmann_chemical under forward Euler only: a
+    context switched to the single-relaxation-time form or to a Runge-Kutta scheme refuses
+    an adjoint step (ESTATE), and accepts it again once switched back."""
     w = W.adjoint_strip(nx=8, ny=3)
     f, lam = _oracle_state(w, _random_fields(8, 3, 11), steps=1)
     s = _sim(w)
@@ -133,6 +133,10 @@ def test_adjoint_step_refuses_the_srt_form():
     with pytest.raises(_lbkm().LbkmError, match="MRT"):
         s.adjoint_step(*args, torch.zeros(NG, dtype=torch.float64, device=dev))
     s.set_srt(0.0)
+    s.set_time_scheme(3)
+    with pytest.raises(_lbkm().LbkmError, match="Euler"):
+        s.adjoint_step(*args, torch.zeros(NG, dtype=torch.float64, device=dev))
+    s.set_time_scheme(1)
     s.adjoint_step(*args, torch.zeros(NG, dtype=torch.float64, device=dev))
     torch.cuda.synchronize()
 

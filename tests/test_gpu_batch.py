@@ -89,13 +89,14 @@ def test_ragged_edge_batch_matches_oracle_per_instance():
         _assert_parity_with_oracle(spec, k, per[k], 300, "edge batch")
 
 
-def test_batch_refuses_the_srt_switch():
-    """The single-relaxation-time form is a single-grid option; a batched context refuses
-    it (ESTATE) and keeps stepping in the MRT form."""
+def test_batch_refuses_the_srt_switch_and_runge_kutta():
+    """The single-relaxation-time form and the Runge-Kutta schemes are single-grid options;
+    a batched context refuses them (ESTATE) and keeps stepping in the MRT form."""
     L = _lbkm()
     b = L.batch_from_spec(_edge_spec())
     assert b.lib.lbkm_set_srt(b.h, 1e-3) == -5
     assert "batched" in b.lib.lbkm_last_error(b.h).decode()
+    assert b.lib.lbkm_set_time_scheme(b.h, 2) == -5
     b.step(2)
     b.status()
 

@@ -173,6 +173,24 @@ def test_srt_collision_matches_oracle(case):
         assert 0.0 < g["lam"][0, 200:].max() < 1.0
 
 
+@pytest.mark.parametrize("rk", [2, 3])
+@pytest.mark.parametrize("case", ["sod", "det-amod"])
+def test_runge_kutta_time_schemes_match_oracle(rk, case):
+    """SSP-RK2 and SSP-RK3 (lbkm_set_time_scheme): Sod 400 x 1 for 1000 steps, and the
+    detonation on 400 x 3 cells for 300 steps with A_hat active (R_8 = 2 R_5, R_9 = 1.5 R_7:
+    the velocity planes must follow every stage) and the reaction running."""
+    if case == "sod":
+        w = W.sod(steps=1000).with_(rk=rk)
+    else:
+        w = W.detonation(nx=400, ny=3, steps=300).with_(R=W.rates(100.0, r8=200.0, r9=150.0), rk=rk)
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    assert P.rk == rk
+    _assert_parity(g, P, tab, f, lam, label=f"rk{rk} {case}")
+    if case == "det-amod":
+        assert 0.0 < g["lam"][0, 200:].max() < 1.0
+
+
 def _window_oracle(w, fields, cells, K):
     """Advance the oracle K steps on a (4K+1)^2 window around each cell (periodic wrap in
     x and y) and return the centre cell's moments."""
@@ -272,8 +290,10 @@ VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 
                                                                          bc_y="outflow"),
                                W.kh(n=2048, steps=30).with_(nx=130, ny=67),
                                W.kh(n=2048, steps=20).with_(nx=2040, ny=9),
-                               W.kh(n=2048, steps=30).with_(nx=130, ny=67, tau=1.0 / 2e4)],
-                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67"])
+                               W.kh(n=2048, steps=30).with_(nx=130, ny=67, tau=1.0 / 2e4),
+                               W.detonation(nx=333, ny=7, steps=12).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
+                                                                         bc_y="outflow", rk=3)],
+                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67", "det-amod-rk3-333x7"])
 def test_launch_variants_give_bitwise_identical_results(w):
     """Every compiled launch shape (LDS-staged or not) in both tile orders computes the same
     bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the

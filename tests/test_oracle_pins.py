@@ -164,6 +164,48 @@ def test_relaxation_closed_form_pins_euler_and_rate_indices():
     assert not torch.allclose(got, rk2, rtol=1e-3)
 
 
+@pytest.mark.parametrize("rk", [2, 3])
+def test_runge_kutta_relaxation_closed_form(rk):
+    """The SSP Runge-Kutta schemes (Shu and Osher 1988) on the uniform relaxation of the
+    forward-Euler pin: every non-conserved moment decays as p(R_k dt)^n with the schemes'
+    stability polynomials p(x) = 1 - x + x^2/2 (RK2) and 1 - x + x^2/2 - x^3/6 (RK3), exact
+    for this linear, autonomous problem.  Forward Euler's (1 - x)^n must not fit."""
+    R = tuple(2000.0 + 1731.0 * k for k in range(24))
+    P = _params(R=R, dt=2e-5, bc_x="periodic", bc_y="periodic", rk=rk)
+    tab = om.make_tables(P)
+    t = lambda v: torch.full((2, 3), v, dtype=T64)
+    feq = om.equilibrium_moments(t(1.1), t(0.2), t(-0.1), t(1.3), P.I)
+    delta = torch.zeros(24, dtype=T64)
+    delta[4:] = 1e-3 * torch.linspace(-1.0, 1.0, 20, dtype=T64) * feq[4:, 0, 0].abs()
+    f = torch.einsum("ik,k...->i...", tab.Minv, feq + delta.reshape(-1, 1, 1))
+    n = 6
+    f, lam = om.run(f, torch.zeros(2, 3, dtype=T64), P, tab, n)
+    fhat = om.moment_transform(f, tab)
+    got = (fhat - om.equilibrium_moments(*om.macroscopic(fhat, P.I), P.I))[4:, 0, 0]
+    x = torch.tensor([R[k] * P.dt for k in range(4, 24)], dtype=T64)
+    poly = 1 - x + x ** 2 / 2 - (x ** 3 / 6 if rk == 3 else 0.0)
+    assert torch.allclose(got, poly ** n * delta[4:], rtol=1e-7, atol=1e-9 * delta.abs().max())
+    assert not torch.allclose(got, (1 - x) ** n * delta[4:], rtol=1e-3)
+
+
+def test_runge_kutta_steps_conserve_mass_and_momentum():
+    """Each stage is a forward-Euler update (conservative NND fluxes, conserving collision)
+    and the stages combine with weights summing to one, so an RK3 run on a periodic grid
+    keeps total mass and momentum to rounding (the reaction, running in every cell here,
+    changes neither); weights not summing to one would not."""
+    g = np.random.default_rng(9)
+    F = dict(rho=1.0 + 0.2 * g.random((6, 7)), ux=0.1 * g.standard_normal((6, 7)),
+             uy=0.1 * g.standard_normal((6, 7)), T=1.25 + 0.3 * g.random((6, 7)), lam=np.zeros((6, 7)))
+    w = W.detonation(nx=7, ny=6, steps=5).with_(bc_x="periodic", bc_y="periodic", T_ig=1.0, rk=3)
+    P, tab, f0, _ = oracle_init(w, fields=F)
+    _, _, f, _ = oracle_run(w, fields=F)
+    h0, h1 = om.moment_transform(f0, tab), om.moment_transform(f, tab)
+    for k in range(3):
+        a, b = float(h0[k].sum()), float(h1[k].sum())
+        assert abs(a - b) < 1e-12 * max(abs(a), float(h0[0].sum())), k
+    assert float((f - f0).abs().max()) > 1e-4
+
+
 def test_srt_step_equals_mrt_step_with_equal_rates():
     """Eq. SRT against Eq. MRT (Sec. V): with every R_k = 1/tau, M^-1 R (f_hat - f_hat^eq)
     = (f - M^-1 f_hat^eq)/tau and A_hat vanishes (R_8 = R_5, R_9 = R_7), so one SRT step
