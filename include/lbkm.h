@@ -160,6 +160,27 @@ lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical);
  * waited for, once buffers and parameters are set). */
 lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau);
 
+/* Wall boundary of one side of the grid (Sec. IV C shock reflection, Sec. IV D Couette
+ * flow), overriding the axis rule of lbkm_grid.bc_x / bc_y on that side.  side: 0 = x low,
+ * 1 = x high, 2 = y low, 3 = y high.  The wall lies on the face between the edge cells and
+ * two ghost layers whose distributions the library fills before every step (and every
+ * Runge-Kutta stage) from the current state:
+ *   type 0: none (the axis rule: periodic wrap or zero-gradient outflow);
+ *   type 1: reflecting (specular) wall: ghost layer k holds the edge layer k with the
+ *           velocities mirrored across the wall, lambda alike; no mass, energy or
+ *           tangential momentum crosses it;
+ *   type 2: Dirichlet: both layers hold the discrete equilibrium M^-1 f_hat^eq of
+ *           state = {rho, T, u_x, u_y, lambda} (inflow, far field);
+ *   type 3: non-equilibrium extrapolation: both layers hold the equilibrium at the edge
+ *           cell's density and the wall's T = state[1], u = (state[2], state[3]) plus the
+ *           edge cell's non-equilibrium part f - f^eq; lambda copies the edge cell.
+ * state: host array of 5 doubles (used by types 2 and 3; may be NULL for 0 and 1).  A wall
+ * needs bc = LBKM_BC_OUTFLOW on its axis (the opposite side keeps that rule unless it is a
+ * wall too).  With a wall the step uses the 256 x 2 direct launch shape.  Errors: EINVAL
+ * for a bad side, type, axis rule or state (non-finite, rho <= 0 or T <= 0); ESTATE on a
+ * batched context.  lbkm_adjoint_step refuses a context with walls (ESTATE). */
+lbkm_status lbkm_set_boundary(lbkm_ctx* ctx, int32_t side, int32_t type, const double* state);
+
 /* Time integration of the single-grid step.  order = 1: forward Euler (the default, the
  * reading of Eq. Boltzmann_chemical's time derivative used throughout); order = 2: the
  * two-stage and order = 3: the three-stage strong-stability-preserving Runge-Kutta schemes

@@ -37,7 +37,7 @@ ones the GPU library takes):
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 import torch
@@ -69,6 +69,10 @@ class Params:
     bc_y: str = PERIODIC
     tau: float = 0.0              # > 0: single-relaxation-time collision of Eq. SRT (Sec. V)
     rk: int = 1                   # time scheme: 1 forward Euler, 2 / 3 SSP Runge-Kutta
+    # boundaries of single sides that override bc_x / bc_y: {"x_lo" | "x_hi" | "y_lo" |
+    # "y_hi": spec}, spec = ("reflect",) | ("dirichlet", rho, T, u_x, u_y, lambda) |
+    # ("nee", T, u_x, u_y)  (see wall_layers)
+    walls: Optional[dict] = None
 
 
 @dataclass
@@ -169,6 +173,89 @@ def ghost(a: torch.Tensor, dim: int, bc: str, w: int = 2) -> torch.Tensor:
     return a.index_select(dim, idx)
 
 
+def mirror_permutation(tab: Tables, axis: str) -> torch.Tensor:
+    """Index j(i) of the velocity v_j that is v_i mirrored across a wall normal to `axis`
+    (v_x -> -v_x for "x", v_y -> -v_y for "y"; eta is the same within a group)."""
+    vx, vy, eta = tab.vx.numpy(), tab.vy.numpy(), tab.eta.numpy()
+    perm = []
+    for i in range(len(vx)):
+        tx, ty = (-vx[i], vy[i]) if axis == "x" else (vx[i], -vy[i])
+        j = [k for k in range(len(vx)) if vx[k] == tx and vy[k] == ty and eta[k] == eta[i]]
+        assert len(j) == 1
+        perm.append(j[0])
+    return torch.tensor(perm)
+
+
+def _edge_layer(a: torch.Tensor, dim: int, side: str, k: int) -> torch.Tensor:
+    """Layer k of `a` counted from the edge of `side` (k = 0: the edge cell), kept as a
+    slice of width 1 along dim; layers beyond the grid repeat its far edge."""
+    n = a.shape[dim]
+    k = min(k, n - 1)
+    return a.narrow(dim, k if side.endswith("lo") else n - 1 - k, 1)
+
+
+def wall_layers(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables, side: str, spec):
+    """The two ghost layers (nearest the edge first) of f [24, Ny, Nx] and lambda [Ny, Nx]
+    beyond one side of the grid.  The wall sits on the face between the edge cell and
+    the first ghost.  The paper names these boundaries (Sec. IV C, IV D) without
+    formulas; the readings are:
+      reflect:   specular wall; ghost layer k holds the distributions of interior layer k
+                 with mirrored velocities (f_i <- f_{mirror(i)}), lambda mirrored alike;
+      dirichlet: both layers hold the discrete equilibrium M^-1 f_hat^eq of the given
+                 (rho, T, u_x, u_y), and the given lambda;
+      nee:       non-equilibrium extrapolation: both layers hold the equilibrium at the
+                 edge cell's density and the wall's (T, u_x, u_y) plus the edge cell's
+                 non-equilibrium part f - f^eq; lambda copies the edge cell."""
+    axis = side[0]
+    fd, ld = (2, 1) if axis == "x" else (1, 0)
+    kind = spec[0]
+    if kind == "reflect":
+        perm = mirror_permutation(tab, axis)
+        fl = [_edge_layer(f, fd, side, k)[perm] for k in (0, 1)]
+        ll = [_edge_layer(lam, ld, side, k) for k in (0, 1)]
+    elif kind == "dirichlet":
+        rho, T, ux, uy, lv = (float(v) for v in spec[1:])
+        e = _edge_layer(f, fd, side, 0)
+        one = torch.ones_like(e[0])
+        feq = torch.einsum("ik,k...->i...", tab.Minv, equilibrium_moments(rho * one, ux * one, uy * one, T * one, P.I))
+        fl = [feq, feq]
+        ll = [torch.full_like(_edge_layer(lam, ld, side, 0), lv)] * 2
+    elif kind == "nee":
+        Tw, uxw, uyw = (float(v) for v in spec[1:])
+        e = _edge_layer(f, fd, side, 0)
+        rho0, ux0, uy0, T0 = macroscopic(moment_transform(e, tab), P.I)
+        one = torch.ones_like(rho0)
+        feq0 = torch.einsum("ik,k...->i...", tab.Minv, equilibrium_moments(rho0, ux0, uy0, T0, P.I))
+        feqw = torch.einsum("ik,k...->i...", tab.Minv, equilibrium_moments(rho0, uxw * one, uyw * one, Tw * one, P.I))
+        g = feqw + (e - feq0)
+        fl = [g, g]
+        ll = [_edge_layer(lam, ld, side, 0)] * 2
+    else:
+        raise ValueError(f"unknown wall type {kind!r}")
+    return fl, ll
+
+
+def padded(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables, axis: str):
+    """f and lambda with two ghost layers per side along `axis` ("x" or "y"): the sides
+    listed in P.walls take wall_layers, the others the axis rule of P.bc_x / P.bc_y
+    (periodic wrap or zero-gradient outflow)."""
+    fd, ld = (2, 1) if axis == "x" else (1, 0)
+    bc = P.bc_x if axis == "x" else P.bc_y
+    fp, lp = ghost(f, fd, bc), ghost(lam, ld, bc)
+    walls = P.walls or {}
+    n = f.shape[fd]
+    # padded positions: 1 and 0 hold layers 0 and 1 of the low side, n+2 and n+3 those of
+    # the high side
+    fparts = [fp.narrow(fd, 0, 1), fp.narrow(fd, 1, 1), f, fp.narrow(fd, n + 2, 1), fp.narrow(fd, n + 3, 1)]
+    lparts = [lp.narrow(ld, 0, 1), lp.narrow(ld, 1, 1), lam, lp.narrow(ld, n + 2, 1), lp.narrow(ld, n + 3, 1)]
+    for side, where in ((axis + "_lo", (1, 0)), (axis + "_hi", (3, 4))):
+        if side in walls:
+            fl, ll = wall_layers(f, lam, P, tab, side, walls[side])
+            for k in (0, 1):
+                fparts[where[k]], lparts[where[k]] = fl[k], ll[k]
+    return torch.cat(fparts, dim=fd), torch.cat(lparts, dim=ld)
+
+
 def minmod(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     """minmod(a, b): the argument of smaller magnitude when a and b have the same
     strict sign, else zero."""
@@ -185,8 +272,12 @@ def nnd_derivative(a: torch.Tensor, dim: int, positive: bool, bc: str, h: float)
     Speed < 0: h_{j+1/2} = a_{j+1} - mm(a_{j+1} - a_j, a_{j+2} - a_{j+1})/2
     and the derivative is (h_{j+1/2} - h_{j-1/2}) / h.
     """
-    g = ghost(a, dim, bc)
-    n = a.shape[dim]
+    return nnd_from_padded(ghost(a, dim, bc), dim, positive, h)
+
+
+def nnd_from_padded(g: torch.Tensor, dim: int, positive: bool, h: float) -> torch.Tensor:
+    """nnd_derivative of an array already padded with two ghost layers per side."""
+    n = g.shape[dim] - 4
     s = lambda k: g.narrow(dim, 2 + k, n)       # a_{j+k}
     am2, am1, a0, ap1, ap2 = s(-2), s(-1), s(0), s(1), s(2)
     if positive:
@@ -198,13 +289,16 @@ def nnd_derivative(a: torch.Tensor, dim: int, positive: bool, bc: str, h: float)
     return (h_plus - h_minus) / h
 
 
-def streaming(f: torch.Tensor, P: Params, T: Tables) -> torch.Tensor:
+def streaming(f: torch.Tensor, P: Params, T: Tables, fx=None, fy=None) -> torch.Tensor:
     """v_i_alpha d f_i / d r_alpha with the NND scheme; each f_i is upwinded by
-    the sign of its own velocity component.  f has shape [24, Ny, Nx]."""
-    dxp = nnd_derivative(f, 2, True, P.bc_x, P.dx)
-    dxm = nnd_derivative(f, 2, False, P.bc_x, P.dx)
-    dyp = nnd_derivative(f, 1, True, P.bc_y, P.dy)
-    dym = nnd_derivative(f, 1, False, P.bc_y, P.dy)
+    the sign of its own velocity component.  f has shape [24, Ny, Nx]; fx, fy are f
+    padded along x and y (default: the axis rules of P.bc_x, P.bc_y)."""
+    fx = ghost(f, 2, P.bc_x) if fx is None else fx
+    fy = ghost(f, 1, P.bc_y) if fy is None else fy
+    dxp = nnd_from_padded(fx, 2, True, P.dx)
+    dxm = nnd_from_padded(fx, 2, False, P.dx)
+    dyp = nnd_from_padded(fy, 1, True, P.dy)
+    dym = nnd_from_padded(fy, 1, False, P.dy)
     vx, vy = _b(T.vx, f), _b(T.vy, f)
     dfx = torch.where(vx > 0, dxp, dxm)
     dfy = torch.where(vy > 0, dyp, dym)
@@ -215,17 +309,20 @@ def streaming(f: torch.Tensor, P: Params, T: Tables) -> torch.Tensor:
 # Collision, modification and chemistry
 # --------------------------------------------------------------------------
 
-def modification_terms(rho, ux, uy, T, P: Params, tab: Tables):
+def modification_terms(rho, ux, uy, T, P: Params, tab: Tables, upad=None):
     """A_hat_8 and A_hat_9 (Eqs. ArtificialA8, ArtificialA9) with the velocity
-    gradients taken as second-order central differences."""
+    gradients taken as second-order central differences.  upad (optional): the velocity
+    fields padded by one layer per side, {"x": (u_x, u_y) padded along x, "y": ...};
+    default: the axis rules of P.bc_x, P.bc_y."""
     I = P.I
-    gx = lambda a: ghost(a, 1, P.bc_x, 1)
-    gy = lambda a: ghost(a, 0, P.bc_y, 1)
     nx, ny = rho.shape[1], rho.shape[0]
-    cdx = lambda a: (gx(a)[:, 2:nx + 2] - gx(a)[:, 0:nx]) / (2.0 * P.dx)
-    cdy = lambda a: (gy(a)[2:ny + 2, :] - gy(a)[0:ny, :]) / (2.0 * P.dy)
-    dux_dx, dux_dy = cdx(ux), cdy(ux)
-    duy_dx, duy_dy = cdx(uy), cdy(uy)
+    if upad is None:
+        upad = {"x": (ghost(ux, 1, P.bc_x, 1), ghost(uy, 1, P.bc_x, 1)),
+                "y": (ghost(ux, 0, P.bc_y, 1), ghost(uy, 0, P.bc_y, 1))}
+    cdx = lambda a: (a[:, 2:nx + 2] - a[:, 0:nx]) / (2.0 * P.dx)
+    cdy = lambda a: (a[2:ny + 2, :] - a[0:ny, :]) / (2.0 * P.dy)
+    dux_dx, dux_dy = cdx(upad["x"][0]), cdy(upad["y"][0])
+    duy_dx, duy_dy = cdx(upad["x"][1]), cdy(upad["y"][1])
     R5, R7, R8, R9 = tab.R[4], tab.R[6], tab.R[7], tab.R[8]
     A8 = rho * T * (R5 - R8) / R5 * (
         4.0 * ux * (dux_dx - dux_dx / (D + I) - duy_dy / (D + I))
@@ -297,23 +394,33 @@ def euler_update(f: torch.Tensor, lam: torch.Tensor, P: Params, tab: Tables):
     p = rho * T
     feq_hat = equilibrium_moments(rho, ux, uy, T, P.I)
     feq = torch.einsum("ik,k...->i...", tab.Minv, feq_hat)
+    fx = fy = lx = ly = upad = None
+    if P.walls:
+        # ghost layers from the boundary rules; the velocity at a ghost is the velocity
+        # moment of its distributions
+        fx, lx = padded(f, lam, P, tab, "x")
+        fy, ly = padded(f, lam, P, tab, "y")
+        nx, ny = f.shape[2], f.shape[1]
+        ux_x, uy_x = macroscopic(moment_transform(fx[:, :, 1:nx + 3], tab), P.I)[1:3]
+        ux_y, uy_y = macroscopic(moment_transform(fy[:, 1:ny + 3, :], tab), P.I)[1:3]
+        upad = {"x": (ux_x, uy_x), "y": (ux_y, uy_y)}
     if P.tau > 0:
         omega = collision_srt(f, feq, P.tau)
     else:
-        A8, A9 = modification_terms(rho, ux, uy, T, P, tab)
+        A8, A9 = modification_terms(rho, ux, uy, T, P, tab, upad)
         omega = collision(fhat, feq_hat, A8, A9, tab)
 
     dlam = cochran_increment(lam, p, T, P, tab)
     F = dlam / P.dt
     C = chemical_term(feq, ux, uy, T, F, P, tab)
 
-    adv = streaming(f, P, tab)
+    adv = streaming(f, P, tab, fx, fy)
     f_new = f + P.dt * (-adv - omega + C)
 
-    dlx = torch.where(ux > 0, nnd_derivative(lam, 1, True, P.bc_x, P.dx),
-                      nnd_derivative(lam, 1, False, P.bc_x, P.dx))
-    dly = torch.where(uy > 0, nnd_derivative(lam, 0, True, P.bc_y, P.dy),
-                      nnd_derivative(lam, 0, False, P.bc_y, P.dy))
+    lx = ghost(lam, 1, P.bc_x) if lx is None else lx
+    ly = ghost(lam, 0, P.bc_y) if ly is None else ly
+    dlx = torch.where(ux > 0, nnd_from_padded(lx, 1, True, P.dx), nnd_from_padded(lx, 1, False, P.dx))
+    dly = torch.where(uy > 0, nnd_from_padded(ly, 0, True, P.dy), nnd_from_padded(ly, 0, False, P.dy))
     lam_new = lam + dlam - P.dt * (ux * dlx + uy * dly)
     return f_new, lam_new
 

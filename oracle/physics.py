@@ -116,6 +116,37 @@ def riemann_sample(left, right, g, xi):
 # Detonation states
 # --------------------------------------------------------------------------
 
+def oblique_shock(rho, p, speed, g, theta):
+    """Weak oblique shock that turns a uniform supersonic stream (density rho, pressure p,
+    speed `speed`) by the angle theta (radians, 0 < theta < the detachment angle).  Shock
+    angle beta from the theta-beta-M relation tan(theta) = 2 cot(beta) (M^2 sin^2(beta) - 1) /
+    (M^2 (g + cos 2 beta) + 2), weak root by bisection between the Mach angle and the
+    angle of maximum deflection; downstream state from the normal-shock jumps of the normal
+    Mach number M sin(beta).  Returns dict(beta, rho, p, speed) downstream."""
+    c = math.sqrt(g * p / rho)
+    M = speed / c
+    f = lambda b: 2.0 / math.tan(b) * (M * M * math.sin(b) ** 2 - 1.0) / (M * M * (g + math.cos(2 * b)) + 2.0)
+    lo = math.asin(1.0 / M)
+    grid = [lo + (math.pi / 2 - lo) * k / 2000.0 for k in range(1, 2000)]
+    hi = max(grid, key=f)                       # angle of maximum deflection
+    if f(hi) < math.tan(theta):
+        raise ValueError("deflection beyond the detachment angle")
+    a, b = lo, hi
+    for _ in range(200):
+        m = 0.5 * (a + b)
+        if f(m) < math.tan(theta):
+            a = m
+        else:
+            b = m
+    beta = 0.5 * (a + b)
+    mn = M * math.sin(beta)
+    rho2 = rho * (g + 1.0) * mn * mn / ((g - 1.0) * mn * mn + 2.0)
+    p2 = p * (1.0 + 2.0 * g / (g + 1.0) * (mn * mn - 1.0))
+    mn2 = math.sqrt((1.0 + 0.5 * (g - 1.0) * mn * mn) / (g * mn * mn - 0.5 * (g - 1.0)))
+    M2 = mn2 / math.sin(beta - theta)
+    return {"beta": beta, "rho": rho2, "p": p2, "speed": M2 * math.sqrt(g * p2 / rho2)}
+
+
 def cj_state(rho0, p0, Q, g):
     """Chapman-Jouguet state behind a detonation moving into quiescent gas.
 

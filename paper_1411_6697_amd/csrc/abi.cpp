@@ -117,6 +117,7 @@ lbkm_status build_tables(lbkm_ctx* ctx, const lbkm_grid* g) {
     c.ny = g->ny;
     c.bc_x = g->bc_x;
     c.bc_y = g->bc_y;
+    c.gL = g->nx > g->ny ? g->nx : g->ny;
     return LBKM_OK;
 }
 
@@ -272,6 +273,21 @@ static lbkm_status rk3_ready(lbkm_ctx* ctx, bool amod) {
     return LBKM_OK;
 }
 
+static bool any_wall(const lbkm_ctx* ctx) {
+    for (int k = 0; k < 4; ++k)
+        if (ctx->h.wall[k] != kWallNone) return true;
+    return false;
+}
+
+// ghost buffer of the wall sides, library-owned
+static lbkm_status ghost_ready(lbkm_ctx* ctx) {
+    const int64_t n = (int64_t)kGhostPlanes * 8 * ctx->h.gL;
+    if (ctx->gbuf) return LBKM_OK;
+    hipError_t e = hipMalloc((void**)&ctx->gbuf, sizeof(double) * n);
+    if (e != hipSuccess) return hip_fail(ctx, e, "allocation of the ghost layers");
+    return LBKM_OK;
+}
+
 lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
@@ -287,26 +303,38 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
         st = rk3_ready(ctx, amod);
         if (st != LBKM_OK) return st;
     }
+    const bool walls = any_wall(ctx);
+    if (walls) {
+        st = ghost_ready(ctx);
+        if (st != LBKM_OK) return st;
+    }
     const int nx = ctx->grid.nx, ny = ctx->grid.ny, var = ctx->step_variant, ord = ctx->tile_order;
+    double* gb = walls ? ctx->gbuf : nullptr;
+    // one stage: the ghost layers of its input state (wall sides), then the step kernel
+    auto stage = [&](const double* fi, double* fo, const double* li, double* lo, const double* ui, double* uo,
+                     const Blend* bl) {
+        if (walls) {
+            hipError_t e = launch_ghost(ctx->d, nx, ny, fi, li, gb, ctx->stream);
+            if (e != hipSuccess) return e;
+        }
+        return launch_step(ctx->d, var, flags, nx, ny, fi, fo, li, lo, ui, uo, ord, ctx->stream, bl, gb);
+    };
     for (int64_t k = 0; k < n; ++k) {
         const int a = ctx->cur, b = 1 - a;
         double *fa = ctx->f[a], *fb = ctx->f[b], *la = ctx->lam[a], *lb = ctx->lam[b];
         double *ua = ctx->u[a], *ub = ctx->u[b];
         // forward Euler, and the first stage of both Runge-Kutta schemes: state b = E(state a)
-        hipError_t e = launch_step(ctx->d, var, flags, nx, ny, fa, fb, la, lb, ua, ub, ord, ctx->stream);
+        hipError_t e = stage(fa, fb, la, lb, ua, ub, nullptr);
         if (e == hipSuccess && ctx->rk == 2) {
             // f^{n+1} = f^n / 2 + E(g_1) / 2, written over f^n
             const Blend bl{nullptr, nullptr, 0.5, 0.5};
-            e = launch_step(ctx->d, var, flags, nx, ny, fb, fa, lb, la, ub, ua, ord, ctx->stream, &bl);
+            e = stage(fb, fa, lb, la, ub, ua, &bl);
         } else if (e == hipSuccess && ctx->rk == 3) {
             // g_2 = 3/4 f^n + 1/4 E(g_1); f^{n+1} = 1/3 f^n + 2/3 E(g_2), written over f^n
             const Blend b2{fa, la, 0.75, 0.25};
-            e = launch_step(ctx->d, var, flags, nx, ny, fb, ctx->f3, lb, ctx->lam3, ub, ctx->u3, ord, ctx->stream,
-                            &b2);
+            e = stage(fb, ctx->f3, lb, ctx->lam3, ub, ctx->u3, &b2);
             const Blend b3{nullptr, nullptr, 1.0 / 3.0, 2.0 / 3.0};
-            if (e == hipSuccess)
-                e = launch_step(ctx->d, var, flags, nx, ny, ctx->f3, fa, ctx->lam3, la, ctx->u3, ua, ord,
-                                ctx->stream, &b3);
+            if (e == hipSuccess) e = stage(ctx->f3, fa, ctx->lam3, la, ctx->u3, ua, &b3);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
         if (ctx->rk == 1) ctx->cur = b;
@@ -408,6 +436,27 @@ lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau) {
     return ctx->bound && ctx->params ? upload_consts(ctx) : LBKM_OK;
 }
 
+lbkm_status lbkm_set_boundary(lbkm_ctx* ctx, int32_t side, int32_t type, const double* state) {
+    if (!ctx) return LBKM_EINVAL;
+    if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
+    if (side < 0 || side > 3) return fail(ctx, LBKM_EINVAL, "side must be 0..3 (x_lo, x_hi, y_lo, y_hi)");
+    if (type < kWallNone || type > kWallNee) return fail(ctx, LBKM_EINVAL, "unknown boundary type");
+    const int axis_bc = side < 2 ? ctx->grid.bc_x : ctx->grid.bc_y;
+    if (type != kWallNone && axis_bc != LBKM_BC_OUTFLOW)
+        return fail(ctx, LBKM_EINVAL, "a wall side needs the outflow rule on its axis (the other side keeps it)");
+    double v[5] = {0, 0, 0, 0, 0};
+    if (type == kWallDirichlet || type == kWallNee) {
+        if (!state) return fail(ctx, LBKM_EINVAL, "this boundary type needs a state");
+        std::memcpy(v, state, sizeof(v));
+        if (!finite_all(v, 5)) return fail(ctx, LBKM_EINVAL, "non-finite boundary state");
+        if (!(v[1] > 0.0) || (type == kWallDirichlet && !(v[0] > 0.0)))
+            return fail(ctx, LBKM_EINVAL, "boundary density and temperature must be > 0");
+    }
+    ctx->h.wall[side] = type;
+    std::memcpy(ctx->h.wall_state[side], v, sizeof(v));
+    return ctx->bound && ctx->params ? upload_consts(ctx) : LBKM_OK;
+}
+
 lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order) {
     if (!ctx) return LBKM_EINVAL;
     if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
@@ -426,6 +475,16 @@ lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
+    if (any_wall(ctx)) {   // wall sides run one shape (256 x 2, direct loads); nothing to tune
+        ctx->step_variant = 3;
+        if (choice) {
+            choice[0] = 256;
+            choice[1] = 2;
+            choice[2] = 0;
+            choice[3] = ctx->tile_order;
+        }
+        return LBKM_OK;
+    }
     const int64_t cells = ctx->pitch * (int64_t)ctx->grid.ny;
     const int cur = ctx->cur;
     const int64_t steps0 = ctx->steps;
@@ -516,7 +575,7 @@ lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
     if (ctx->adj_scratch) (void)hipFree(ctx->adj_scratch);
     for (int i = 0; i < 2; ++i)
         if (ctx->u[i]) (void)hipFree(ctx->u[i]);
-    for (double* p : {ctx->f3, ctx->lam3, ctx->u3})
+    for (double* p : {ctx->f3, ctx->lam3, ctx->u3, ctx->gbuf})
         if (p) (void)hipFree(p);
     delete ctx;
     return LBKM_OK;

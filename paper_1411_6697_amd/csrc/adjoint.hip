@@ -804,6 +804,9 @@ lbkm_status lbkm_adjoint_step(lbkm_ctx* ctx, const double* f_n, const double* la
     if (st != LBKM_OK) return st;
     if (ctx->h.srt) return fail(ctx, LBKM_ESTATE, "the adjoint step covers the MRT form only");
     if (ctx->rk != 1) return fail(ctx, LBKM_ESTATE, "the adjoint step covers forward Euler only");
+    for (int k = 0; k < 4; ++k)
+        if (ctx->h.wall[k] != kWallNone)
+            return fail(ctx, LBKM_ESTATE, "the adjoint step covers periodic and outflow boundaries only");
     if (!f_n || !lam_n || !af_np1 || !alam_np1 || !af_n || !alam_n || !grad_params)
         return fail(ctx, LBKM_EINVAL, "NULL argument");
     if (af_n == af_np1 || alam_n == alam_np1)

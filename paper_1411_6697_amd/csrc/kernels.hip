@@ -206,6 +206,91 @@ __global__ __launch_bounds__(256) void k_velocity(const Consts* __restrict__ c, 
     u[c->plane + at] = va.jy / va.r;
 }
 
+// Ghost layers of the wall sides (Sec. IV C, IV D name the boundaries without formulas):
+//   reflect:   layer k holds interior layer k with mirrored velocities, lambda alike;
+//   dirichlet: both layers hold the discrete equilibrium of the given state and lambda;
+//   nee:       both layers hold f^eq(rho_edge, wall T and u) + (f - f^eq) of the edge cell,
+//              lambda copies the edge cell;
+// and the velocity planes hold the velocity moment of the ghost distributions.
+// One thread per (side, position along the side).
+__global__ __launch_bounds__(256) void k_ghost(const Consts* __restrict__ c, const double* __restrict__ f,
+                                               const double* __restrict__ lam, double* __restrict__ gb) {
+    const int side = blockIdx.y;
+    const int type = c->wall[side];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = c->nx, ny = c->ny;
+    if (type == kWallNone || j >= (side < 2 ? ny : nx)) return;
+    const int64_t L = c->gL, gplane = 8 * L;
+    // mirror of direction d across a wall normal to x (sides 0, 1) or to y (sides 2, 3)
+    constexpr int kMirrorX[8] = {2, 1, 0, 3, 5, 4, 7, 6};
+    constexpr int kMirrorY[8] = {0, 3, 2, 1, 7, 6, 5, 4};
+    auto cell = [&](int k) -> int64_t {                 // interior layer k from the edge
+        int x, y;
+        if (side < 2) {
+            const int kk = k < nx ? k : nx - 1;
+            x = side == 0 ? kk : nx - 1 - kk;
+            y = j;
+        } else {
+            const int kk = k < ny ? k : ny - 1;
+            y = side == 2 ? kk : ny - 1 - kk;
+            x = j;
+        }
+        return (int64_t)y * c->pitch + x;
+    };
+    auto put = [&](int layer, int p, double v) { gb[p * gplane + (side * 2 + layer) * L + j] = v; };
+    double g[NV];
+    for (int layer = 0; layer < 2; ++layer) {
+        if (type == kWallReflect || layer == 0) {
+            const int64_t at = cell(type == kWallReflect ? layer : 0);
+            double fc[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) fc[i] = f[i * c->plane + at];
+            const double lc = lam[at];
+            if (type == kWallReflect) {
+#pragma unroll
+                for (int gg = 0; gg < 3; ++gg)
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) g[8 * gg + d] = fc[8 * gg + (side < 2 ? kMirrorX[d] : kMirrorY[d])];
+                put(layer, NV, lc);
+            } else {
+                const double* st = c->wall_state[side];
+                double feqw[NV];
+                Blocks e, se;
+                if (type == kWallDirichlet) {
+                    equilibrium(st[0], st[2], st[3], st[1], c->I, e);
+                    inverse(c->mat, e, se);
+                    from_combos(se, g);
+                    put(0, NV, st[4]);
+                } else {
+                    const Macro m = macro_sums(c, fc);
+                    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+                    inverse(c->mat, e, se);
+                    double feq0[NV];
+                    from_combos(se, feq0);
+                    equilibrium(m.rho, st[2], st[3], st[1], c->I, e);
+                    inverse(c->mat, e, se);
+                    from_combos(se, feqw);
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) g[i] = feqw[i] + (fc[i] - feq0[i]);
+                    put(0, NV, lc);
+                }
+            }
+        } else {
+            put(1, NV, gb[NV * gplane + (side * 2) * L + j]);   // the second layer repeats the first
+        }
+        VelAcc va;
+#pragma unroll
+        for (int gg = 0; gg < 3; ++gg)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                put(layer, 8 * gg + d, g[8 * gg + d]);
+                vel_add(va, c, gg, d, g[8 * gg + d]);
+            }
+        put(layer, NV + 1, va.jx / va.r);
+        put(layer, NV + 2, va.jy / va.r);
+    }
+}
+
 // pitched <-> dense copies of the state
 __global__ __launch_bounds__(256) void k_copy_state(const Consts* __restrict__ c, const double* __restrict__ src,
                                                     double* __restrict__ dst, int planes, int to_dense) {
@@ -273,6 +358,13 @@ hipError_t launch_check(const Consts* dc, int nx, int ny, const double* f, const
 
 hipError_t launch_velocity(const Consts* dc, int nx, int ny, const double* f, double* u, hipStream_t st) {
     hipLaunchKernelGGL(k_velocity, row_grid(nx, ny), dim3(256), 0, st, dc, f, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost(const Consts* dc, int nx, int ny, const double* f, const double* lam, double* gb,
+                        hipStream_t st) {
+    const int len = nx > ny ? nx : ny;
+    hipLaunchKernelGGL(k_ghost, dim3((len + 255) / 256, 4), dim3(256), 0, st, dc, f, lam, gb);
     return hipGetLastError();
 }
 

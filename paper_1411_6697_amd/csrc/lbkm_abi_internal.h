@@ -41,6 +41,7 @@ struct lbkm_ctx {
     double* lam3 = nullptr;
     double* u3 = nullptr;
     int64_t rk3_plane = 0;
+    double* gbuf = nullptr;            // ghost layers of the wall sides [27][4][2][max(nx, ny)]
     double* adj_scratch = nullptr;     // adjoint step: U, W planes and parameter partials
     int64_t adj_scratch_n = 0;
     std::string err;

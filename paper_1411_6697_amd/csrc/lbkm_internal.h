@@ -45,7 +45,18 @@ struct Consts {
     int32_t m_is_one, n_is_one;   // exponents equal to 1 (p^1 = p exactly)
     int32_t nx, ny, bc_x, bc_y;   // grid (batched kernels: nx unused)
     int64_t pitch, plane;         // row pitch and plane stride (elements)
+    // wall boundaries of single sides (x_lo, x_hi, y_lo, y_hi): kWall* type, and for
+    // Dirichlet / non-equilibrium-extrapolation walls the state (rho, T, u_x, u_y, lambda)
+    int32_t wall[4];
+    int32_t gL;                   // ghost buffer row length max(nx, ny)
+    double wall_state[4][5];
 };
+
+// wall types of lbkm_set_boundary (0: the axis rule of bc_x / bc_y)
+constexpr int kWallNone = 0, kWallReflect = 1, kWallDirichlet = 2, kWallNee = 3;
+// ghost buffer gb[kGhostPlanes][4 sides][2 layers][gL]: planes 0..23 f, 24 lambda, 25 u_x,
+// 26 u_y; layer 0 is the ghost next to the edge cell
+constexpr int kGhostPlanes = NV + 3;
 
 // Host: fill the velocity model and the block matrices of `c` from the DVM parameters.
 // Returns 0 on success, -2 if M is singular or cond_inf(M) > 1e12; *cond receives the

@@ -23,10 +23,14 @@ struct Blend {
     const double* ln;
     double a, b;
 };
-// bl == nullptr: a plain forward-Euler step
+// bl == nullptr: a plain forward-Euler step.  gb != nullptr: some side is a wall; gb holds
+// the ghost layers of the input state (launch_ghost) and the 256 x 2 direct shape is used.
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
-                       int vertical, hipStream_t st, const Blend* bl = nullptr);
+                       int vertical, hipStream_t st, const Blend* bl = nullptr, const double* gb = nullptr);
+// ghost layers of the wall sides of state (f, lam) into gb [kGhostPlanes][4][2][gL]
+hipError_t launch_ghost(const Consts* dc, int nx, int ny, const double* f, const double* lam, double* gb,
+                        hipStream_t st);
 // velocity planes u[2][plane] of a state (pitched layout of the constants)
 hipError_t launch_velocity(const Consts* dc, int nx, int ny, const double* f, double* u, hipStream_t st);
 hipError_t launch_init(const Consts* dc, int nx, int ny, const double* rho, const double* ux,

@@ -51,14 +51,63 @@ __device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int
     return s;
 }
 
+// Stencil points that fall on a wall side's ghost layers (sides with kWall* != none):
+// bit k of `is` set for point k (0 x-2, 1 x-1, 2 x+1, 3 x+2, 4 y-2, 5 y-1, 6 y+1, 7 y+2),
+// off[k] its byte offset within a ghost-buffer plane (0 where not a ghost, a valid address).
+struct Ghosts {
+    uint32_t off[8];
+    uint32_t is;
+};
+
+__device__ __forceinline__ Ghosts ghosts_of(const Consts* __restrict__ c, int x, int y) {
+    Ghosts g;
+    g.is = 0;
+    const uint32_t L = (uint32_t)c->gL;
+    auto set = [&](int k, int side, int layer, int along) {
+        g.is |= 1u << k;
+        g.off[k] = ((uint32_t)(side * 2 + layer) * L + (uint32_t)along) * 8u;
+    };
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g.off[k] = 0u;
+    const int nx = c->nx, ny = c->ny;
+    if (c->wall[0] != kWallNone) {
+        if (x < 2) set(0, 0, 1 - x, y);
+        if (x < 1) set(1, 0, 0, y);
+    }
+    if (c->wall[1] != kWallNone) {
+        if (x + 1 >= nx) set(2, 1, x + 1 - nx, y);
+        if (x + 2 >= nx) set(3, 1, x + 2 - nx, y);
+    }
+    if (c->wall[2] != kWallNone) {
+        if (y < 2) set(4, 2, 1 - y, x);
+        if (y < 1) set(5, 2, 0, x);
+    }
+    if (c->wall[3] != kWallNone) {
+        if (y + 1 >= ny) set(6, 3, y + 1 - ny, x);
+        if (y + 2 >= ny) set(7, 3, y + 2 - ny, x);
+    }
+    return g;
+}
+
+// value of stencil point k of one plane: the state, or the ghost buffer on a wall side
+template <bool GHOST>
+__device__ __forceinline__ double sld(const Soa& F, uint32_t so, uint32_t off, const Soa& Gb, uint32_t sg,
+                                      const Ghosts& gh, int k) {
+    const double v = ld(F, so, off);
+    if (!GHOST) return v;
+    const double w = ld(Gb, sg, gh.off[k]);
+    return ((gh.is >> k) & 1u) ? w : v;
+}
+
 // Phase 1 of one cell: src = -Omega + C (the right-hand side without streaming), the
 // reaction increment dlam, lambda and the macroscopic state, from the cell's 24 values at
 // level n (and, when A_hat is active, the four neighbours' velocities, written by the
 // previous step or by k_velocity).  SRT: the single-relaxation-time form of Eq. SRT.
-template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT, bool GHOST = false>
 __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const Mats& M, const Soa& F,
                                             const Soa& L, const Soa& Ui, const Off& s, double src[NV],
-                                            double& dlam, double& lam, Macro& m) {
+                                            double& dlam, double& lam, Macro& m, const Soa* Gb = nullptr,
+                                            const Ghosts* gh = nullptr) {
     double f[NV];
     if (SRT) {
         load_cell(F, s.c, f);
@@ -69,7 +118,15 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
     }
     // velocity gradients for A_hat first, so only four numbers are carried on
     double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
-    if (AMOD) {
+    if (AMOD && GHOST) {
+        // velocities of the ghost points come from the ghost buffer's velocity planes
+        const uint32_t up = opaque(Ui.plane_bytes), gp = opaque(Gb->plane_bytes);
+        const uint32_t gx0 = (NV + 1) * gp, gy0 = (NV + 2) * gp;
+        gxx = (sld<true>(Ui, 0u, s.xp1, *Gb, gx0, *gh, 2) - sld<true>(Ui, 0u, s.xm1, *Gb, gx0, *gh, 1)) * c->half_inv_dx;
+        gyx = (sld<true>(Ui, up, s.xp1, *Gb, gy0, *gh, 2) - sld<true>(Ui, up, s.xm1, *Gb, gy0, *gh, 1)) * c->half_inv_dx;
+        gxy = (sld<true>(Ui, 0u, s.yp1, *Gb, gx0, *gh, 6) - sld<true>(Ui, 0u, s.ym1, *Gb, gx0, *gh, 5)) * c->half_inv_dy;
+        gyy = (sld<true>(Ui, up, s.yp1, *Gb, gy0, *gh, 6) - sld<true>(Ui, up, s.ym1, *Gb, gy0, *gh, 5)) * c->half_inv_dy;
+    } else if (AMOD) {
         const uint32_t up = opaque(Ui.plane_bytes);
         gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
         gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
@@ -91,12 +148,12 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
 // AMOD: A_hat can be non-zero; CHEM: the reaction can run; GEXP: exponents m, n not both 1;
 // SRT: single relaxation time (then AMOD is false); BLEND: a Runge-Kutta stage, the result
 // is bl.a * (f^n, lambda^n) + bl.b * (the forward-Euler update).
-template <bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND, bool GHOST>
 __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Mats& M, int x, int y,
                                           const double* __restrict__ fin, double* __restrict__ fout,
                                           const double* __restrict__ lin, double* __restrict__ lout,
                                           const double* __restrict__ uin, double* __restrict__ uout,
-                                          const Blend& bl) {
+                                          const Blend& bl, const double* __restrict__ gb) {
     const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
     const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
@@ -104,11 +161,15 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
     const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
     const Off s = stencil_offsets(c, x, y);
+    // wall sides: the ghost buffer and which stencil points read it
+    const Soa Gb = soa(GHOST ? gb : fin, 8 * (int64_t)c->gL);
+    Ghosts gh;
+    if (GHOST) gh = ghosts_of(c, x, y);
 
     // Phase 1: collision and chemistry from the 24 centre values -> src = -Omega + C.
     double src[NV], dlam, lam;
     Macro m;
-    cell_source<AMOD, CHEM, GEXP, SRT>(c, M, F, L, Ui, s, src, dlam, lam, m);
+    cell_source<AMOD, CHEM, GEXP, SRT, GHOST>(c, M, F, L, Ui, s, src, dlam, lam, m, &Gb, &gh);
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 2: NND streaming plane by plane; the centre value is read again (a cache hit)
@@ -122,12 +183,14 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const uint32_t so = (uint32_t)(8 * g + d) * pb;
+            const uint32_t sg = GHOST ? (uint32_t)(8 * g + d) * Gb.plane_bytes : 0u;
+            auto at = [&](uint32_t off, int k) { return sld<GHOST>(F, so, off, Gb, sg, gh, k); };
             const double f0 = ld(F, so, s.c);
             double adv = 0.0;
-            if (DUX[d] > 0) adv += v * (nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)) * idx_);
-            if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)) * idx_);
-            if (DUY[d] > 0) adv += v * (nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)) * idy);
-            if (DUY[d] < 0) adv -= v * (nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)) * idy);
+            if (DUX[d] > 0) adv += v * (nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)) * idx_);
+            if (DUX[d] < 0) adv -= v * (nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)) * idx_);
+            if (DUY[d] > 0) adv += v * (nnd_pos(at(s.ym2, 4), at(s.ym1, 5), f0, at(s.yp1, 6)) * idy);
+            if (DUY[d] < 0) adv -= v * (nnd_neg(at(s.ym1, 5), f0, at(s.yp1, 6), at(s.yp2, 7)) * idy);
             double out = f0 + dt * (src[8 * g + d] - adv);
             if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
             if (AMOD) vel_add(va, c, g, d, out);
@@ -138,10 +201,12 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
         st_stream(Uo, 0u, s.c, va.jx / va.r);
         st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
     }
-    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
-                                    : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
-    const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
-                                    : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
+    const uint32_t sl = GHOST ? NV * Gb.plane_bytes : 0u;
+    auto lat = [&](uint32_t off, int k) { return sld<GHOST>(L, 0u, off, Gb, sl, gh, k); };
+    const double dlx = (m.ux > 0.0) ? nnd_pos(lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2))
+                                    : nnd_neg(lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
+    const double dly = (m.uy > 0.0) ? nnd_pos(lat(s.ym2, 4), lat(s.ym1, 5), lam, lat(s.yp1, 6))
+                                    : nnd_neg(lat(s.ym1, 5), lam, lat(s.yp1, 6), lat(s.yp2, 7));
     double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
     if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
     st_stream(Lo, 0u, s.c, lnew);
@@ -275,18 +340,18 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
 // general: the reactive specialisations then fit without spilling and the compiler stops
 // parking scalar registers in vector lanes; the general-exponent ones would spill.
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
-__global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND, bool GHOST>
+__global__ __launch_bounds__(TX * TY, (GEXP || GHOST) ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
                                                   double* __restrict__ lout, const double* __restrict__ uin,
                                                   double* __restrict__ uout, int gx, int ntiles, int vertical,
-                                                  Blend bl) {
+                                                  Blend bl, const double* __restrict__ gb) {
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c->nx || y >= c->ny) return;
-    step_cell<AMOD, CHEM, GEXP, SRT, BLEND>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout, bl);
+    step_cell<AMOD, CHEM, GEXP, SRT, BLEND, GHOST>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout, bl, gb);
 }
 
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
@@ -302,28 +367,29 @@ __global__ __launch_bounds__(TX * TY) void k_step_lds(const Consts* __restrict__
                                                         bl, patch);
 }
 
-template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
+template <int TX, int TY, bool LDS, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND, bool GHOST>
 hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, double* fout, const double* lin,
                         double* lout, const double* uin, double* uout, int vertical, hipStream_t st,
-                        const Blend& bl) {
+                        const Blend& bl, const double* gb) {
     const int gx = (nx + TX - 1) / TX, gy = (ny + TY - 1) / TY;
     const int ntiles = gx * gy;
     const int per = (ntiles + kXcds - 1) / kXcds;
-    if (LDS)
+    if constexpr (LDS)
         hipLaunchKernelGGL((k_step_lds<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
     else
-        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0, st, dc,
-                           fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
+        hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND, GHOST>), dim3(per * kXcds), dim3(TX * TY), 0,
+                           st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl, gb);
     return hipGetLastError();
 }
 
-template <int TX, int TY, bool LDS, bool BLEND>
+template <int TX, int TY, bool LDS, bool BLEND, bool GHOST = false>
 hipError_t launch_flags(const Consts* dc, int flags, int nx, int ny, const double* fin, double* fout,
                         const double* lin, double* lout, const double* uin, double* uout, int vertical,
-                        hipStream_t st, const Blend& bl) {
+                        hipStream_t st, const Blend& bl, const double* gb = nullptr) {
 #define LBKM_TILES(A, C, G, S) \
-    launch_tiles<TX, TY, LDS, A, C, G, S, BLEND>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl)
+    launch_tiles<TX, TY, LDS, A, C, G, S, BLEND, GHOST>(dc, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, \
+                                                        bl, gb)
     switch (flags) {
         case 0: return LBKM_TILES(false, false, false, false);
         case 1: return LBKM_TILES(true, false, false, false);
@@ -364,7 +430,15 @@ int step_flags(const Consts& c) {
 
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
-                       int vertical, hipStream_t st, const Blend* bl) {
+                       int vertical, hipStream_t st, const Blend* bl, const double* gb) {
+    if (gb) {
+        // wall sides: the 256 x 2 direct shape, whatever the tuned one
+        if (bl) return launch_flags<256, 2, false, true, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout,
+                                                               vertical, st, *bl, gb);
+        const Blend none{nullptr, nullptr, 0.0, 1.0};
+        return launch_flags<256, 2, false, false, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical,
+                                                        st, none, gb);
+    }
     switch (variant) {
         case 1: return launch_shape<32, 8, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         case 2: return launch_shape<128, 2, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);

@@ -68,6 +68,7 @@ SIGNATURES = {
     "lbkm_set_tile_order": [_P, ctypes.c_int32],
     "lbkm_set_srt": [_P, ctypes.c_double],
     "lbkm_set_time_scheme": [_P, ctypes.c_int32],
+    "lbkm_set_boundary": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "lbkm_autotune": [_P, ctypes.POINTER(ctypes.c_int32)],
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -235,6 +236,22 @@ class Sim:
 
     def set_tile_order(self, vertical: int):
         self._call("lbkm_set_tile_order", ctypes.c_int32(int(vertical)))
+
+    WALL_SIDES = {"x_lo": 0, "x_hi": 1, "y_lo": 2, "y_hi": 3}
+    WALL_TYPES = {"none": 0, "reflect": 1, "dirichlet": 2, "nee": 3}
+
+    def set_boundary(self, side: str, spec):
+        """Wall side: spec = ("reflect",), ("dirichlet", rho, T, u_x, u_y, lambda),
+        ("nee", T, u_x, u_y) or ("none",)."""
+        kind = spec[0]
+        vals = [0.0] * 5
+        if kind == "dirichlet":
+            vals = [float(v) for v in spec[1:6]]
+        elif kind == "nee":
+            vals = [0.0, float(spec[1]), float(spec[2]), float(spec[3]), 0.0]
+        arr = (ctypes.c_double * 5)(*vals)
+        self._call("lbkm_set_boundary", ctypes.c_int32(self.WALL_SIDES[side]),
+                   ctypes.c_int32(self.WALL_TYPES[kind]), arr)
 
     def set_time_scheme(self, order: int):
         """1: forward Euler (default); 2, 3: SSP Runge-Kutta of that order."""
@@ -448,6 +465,8 @@ def sim_from_workload(w, device="cuda:0", pitch=None, fields=None) -> Sim:
         s.set_srt(w.tau)
     if getattr(w, "rk", 1) != 1:
         s.set_time_scheme(w.rk)
+    for side, spec in (getattr(w, "walls", None) or {}).items():
+        s.set_boundary(side, spec)
     F = fields if fields is not None else w.fields()
     s.init_fields(F["rho"], F["ux"], F["uy"], F["T"], F["lam"])
     return s

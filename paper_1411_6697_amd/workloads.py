@@ -58,6 +58,7 @@ class Workload:
     bc_y: str = PERIODIC
     tau: float = 0.0                  # > 0: single-relaxation-time collision (Sec. V)
     rk: int = 1                       # time scheme: 1 forward Euler, 2/3 SSP Runge-Kutta
+    walls: Optional[dict] = None      # per-side wall boundaries overriding bc_x / bc_y
     make_fields: Optional[Callable[["Workload"], Dict[str, np.ndarray]]] = field(default=None, repr=False)
     meta: dict = field(default_factory=dict)
 
@@ -162,6 +163,32 @@ def sjogren(nx: int = 500, ny: int = 1, steps: int = 1500) -> Workload:
         gamma=4.0 / 3.0, I=4.0, R=R, bc_x=OUTFLOW, bc_y=PERIODIC,
         make_fields=_riemann_fields((1.0, -1.2, 0.0, 0.5), (1.0, 1.2, 0.0, 0.5),
                                     lambda w: 0.5 * w.nx * w.dx))
+
+
+DVM_SHOCK_REFLECTION = (1.0, 2.7, 2.9, 1.0, 2.9, 0.96)    # Sec. IV C
+
+
+def shock_reflection(nx: int = 300, ny: int = 100, steps: int = 100000) -> Workload:
+    """Regular shock reflection (Sec. IV C): a 0.3 x 0.1 channel, dx = dy = 1e-3,
+    dt = 5e-6, I = 2 (gamma = 3/2), DVM (1.0, 2.7, 2.9, 1.0, 2.9, 0.96), R_5..R_7 = 1.8e5,
+    R_8 = R_9 = 2e5, other R_k = 1e5; reflecting wall at the bottom, supersonic outflow at
+    the right, Dirichlet inflow (rho, T, u_x, u_y) = (1, 0.5, 2, 0) at the left and the
+    post-shock state (1.25, 0.56, 1.9, -0.173205) at the top; t = 0.5 after 100000 steps.
+    The initial field (not given) is the inflow state everywhere."""
+    R = rates(1e5, r5=1.8e5, r6=1.8e5, r7=1.8e5, r8=2e5, r9=2e5)
+
+    def make(w: Workload):
+        f = _blank(w)
+        f["rho"][...] = 1.0
+        f["T"][...] = 0.5
+        f["ux"][...] = 2.0
+        return f
+    return Workload(
+        name="shock_reflection", nx=nx, ny=ny, dx=1e-3, dy=1e-3, dt=5e-6, steps=steps,
+        dvm=DVM_SHOCK_REFLECTION, gamma=1.5, I=2.0, R=R, bc_x=OUTFLOW, bc_y=OUTFLOW,
+        walls={"x_lo": ("dirichlet", 1.0, 0.5, 2.0, 0.0, 0.0), "y_lo": ("reflect",),
+               "y_hi": ("dirichlet", 1.25, 0.56, 1.9, -0.173205, 0.0)},
+        make_fields=make)
 
 
 # --------------------------------------------------------------------------

@@ -13,7 +13,7 @@ from paper_1411_6697_amd import workloads as W
 def oracle_params(w: W.Workload, **over) -> oracle.Params:
     kw = dict(dvm=oracle.DVM(*w.dvm), I=w.I, R=tuple(w.R), dx=w.dx, dy=w.dy, dt=w.dt, Q=w.Q,
               omega1=w.omega1, omega2=w.omega2, m=w.m, n=w.n, T_ig=w.T_ig,
-              bc_x=w.bc_x, bc_y=w.bc_y, tau=w.tau, rk=w.rk)
+              bc_x=w.bc_x, bc_y=w.bc_y, tau=w.tau, rk=w.rk, walls=w.walls)
     kw.update(over)
     return oracle.Params(**kw)
 

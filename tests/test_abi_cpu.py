@@ -115,6 +115,25 @@ def test_set_time_scheme_validates(order, status):
         _destroy(h)
 
 
+@pytest.mark.parametrize("side,typ,state,status", [
+    (0, 1, None, 0), (1, 2, (1.0, 0.5, 2.0, 0.0, 0.0), 0), (0, 3, (0.0, 1.0, 0.1, 0.0, 0.0), 0), (0, 0, None, 0),
+    (4, 1, None, -1), (0, 4, None, -1), (2, 1, None, -1), (0, 2, None, -1),
+    (0, 2, (0.0, 0.5, 2.0, 0.0, 0.0), -1), (0, 3, (1.0, 0.0, 0.1, 0.0, 0.0), -1),
+    (1, 2, (1.0, float("nan"), 2.0, 0.0, 0.0), -1)])
+def test_set_boundary_validates(side, typ, state, status):
+    """Wall sides (Sec. IV C-D): side 0..3, type 0..3, walls only on an outflow axis (the
+    grid here is outflow in x, periodic in y), Dirichlet needs rho, T > 0, the
+    extrapolation wall T > 0, all finite."""
+    st, h, msg = _create(_grid())
+    assert st == 0, msg
+    try:
+        arr = None if state is None else (ctypes.c_double * 5)(*state)
+        st = L.load().lbkm_set_boundary(h, side, typ, arr)
+        assert st == status, L.load().lbkm_last_error(h).decode()
+    finally:
+        _destroy(h)
+
+
 def test_calls_out_of_order_are_rejected():
     lib = L.load()
     st, h, msg = _create(_grid())

@@ -1,0 +1,95 @@
+"""Wall boundaries (lbkm_set_boundary; Sec. IV C shock reflection, Sec. IV D Couette flow):
+parity of the HIP path with the CPU oracle (max relative error <= 1e-10, the metric of the
+other parity tests) for reflecting, Dirichlet and non-equilibrium-extrapolation sides, with
+A_hat, the reaction, a Runge-Kutta scheme and degenerate grids; and the full shock
+reflection run against the regular-reflection states of oblique-shock theory."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1411_6697_amd import workloads as W
+from tests.helpers import oracle_run
+from tests.test_gpu_parity import _assert_parity, _gpu, _smooth_fields
+
+pytestmark = pytest.mark.gpu
+RATES = W.rates(100.0, r8=200.0, r9=150.0)        # A_hat active
+
+
+def _case(nx, ny, walls, steps, rk=1, seed=3):
+    w = W.detonation(nx=nx, ny=ny, steps=steps).with_(bc_x="outflow", bc_y="outflow", walls=walls, R=RATES,
+                                                       rk=rk, T_ig=1.2)
+    return w, _smooth_fields(nx, ny, seed)
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 29), (2, 3), (1, 5)])
+def test_reflecting_box_matches_oracle(nx, ny):
+    """Reflecting walls on all four sides; smooth random fields with the reaction running
+    where T > 1.2; 37 x 29 cells (several tiles and ragged edges) and grids narrower than
+    the two ghost layers."""
+    walls = {k: ("reflect",) for k in ("x_lo", "x_hi", "y_lo", "y_hi")}
+    w, F = _case(nx, ny, walls, 80)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    _assert_parity(g, P, tab, f, lam, label=f"reflecting box {nx}x{ny}")
+
+
+def test_shock_reflection_boundaries_match_oracle():
+    """The shock-reflection configuration (300 x 100; Dirichlet left and top, reflecting
+    bottom, outflow right) for its first 60 steps.  Later, a mode under the top side grows
+    from rounding (the oracle separates from a copy of itself perturbed by 1e-14 to 5e-10
+    by step 100 and 4e-7 by step 150, with A_hat active; with R_8 = R_5 it does not), so the
+    element-wise bar applies to the early steps."""
+    w = W.shock_reflection(steps=60)
+    s, g = _gpu(w, w.steps)
+    P, tab, f, lam = oracle_run(w)
+    _assert_parity(g, P, tab, f, lam, label="shock reflection, 60 steps")
+
+
+@pytest.mark.parametrize("rk", [1, 2])
+def test_extrapolation_walls_match_oracle(rk):
+    """Non-equilibrium-extrapolation walls at both y sides (the top one moving, the bottom
+    one at another temperature) with a Dirichlet inflow at the left, 16 x 24 cells, 60
+    steps, forward Euler and SSP-RK2 (the ghost layers are refilled for every stage)."""
+    walls = {"y_lo": ("nee", 1.4, 0.0, 0.0), "y_hi": ("nee", 1.3, 0.05, 0.0),
+             "x_lo": ("dirichlet", 1.1, 1.35, 0.08, 0.0, 0.3)}
+    w, F = _case(16, 24, walls, 60, rk=rk)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    _assert_parity(g, P, tab, f, lam, label=f"extrapolation walls rk{rk}")
+
+
+def test_shock_reflection_reaches_the_regular_reflection_state():
+    """Sec. IV C at t = 0.5 (100000 steps on 300 x 100 cells, the HIP path alone): the
+    incident shock from the top-left corner meets the wall at x = 0.1 / tan 30 deg; below
+    the reflected shock the flow runs parallel to the wall in the state that oblique-shock
+    theory gives for turning the post-incident stream back by theta (tan theta =
+    0.173205 / 1.9).  Sampled away from the shocks: the inflow region, the region between
+    the shocks, and the reflected region next to the wall."""
+    from oracle import physics
+    w = W.shock_reflection()
+    s, g = _gpu(w, w.steps)
+    assert s.check()
+    x = (np.arange(w.nx) + 0.5) * w.dx
+    y = (np.arange(w.ny) + 0.5) * w.dy
+    X, Y = np.meshgrid(x, y)
+    gam = 1.5
+    th = math.atan(0.173205 / 1.9)
+    r3 = physics.oblique_shock(1.25, 0.7, math.hypot(1.9, 0.173205), gam, th)
+    xr = 0.1 / math.tan(math.radians(30.0))
+    h3 = lambda xx: (xx - xr) * math.tan(r3["beta"] - th)          # reflected shock height
+    regions = {
+        "1": ((X > 0.02) & (X < 0.06) & (Y < 0.1 - X * math.tan(math.radians(30.0)) - 0.02), (1.0, 0.5, 2.0, 0.0)),
+        "2": ((X > 0.12) & (X < 0.16) & (Y > 0.1 - X * math.tan(math.radians(30.0)) + 0.015) & (Y < 0.09),
+              (1.25, 0.7, 1.9, -0.173205)),
+        "3": ((X > 0.23) & (X < 0.27) & (Y > 0.003) & (Y < 0.6 * h3(0.23)), (r3["rho"], r3["p"], r3["speed"], 0.0)),
+    }
+    for name, (mask, (rho_e, p_e, ux_e, uy_e)) in regions.items():
+        assert mask.sum() >= 6, name
+        rho, p, ux, uy = (float(np.mean(g[k][mask])) for k in ("rho", "p", "ux", "uy"))
+        print(f"region {name}: rho {rho:.4f} ({rho_e:.4f})  p {p:.4f} ({p_e:.4f})  "
+              f"u_x {ux:.4f} ({ux_e:.4f})  u_y {uy:.4f} ({uy_e:.4f})  cells {int(mask.sum())}", flush=True)
+        assert abs(rho - rho_e) < 0.02 * rho_e and abs(p - p_e) < 0.02 * p_e, name
+        assert abs(ux - ux_e) < 0.02 * ux_e and abs(uy - uy_e) < 0.02 * ux_e, name

@@ -206,6 +206,93 @@ def test_runge_kutta_steps_conserve_mass_and_momentum():
     assert float((f - f0).abs().max()) > 1e-4
 
 
+# ---------------------------------------------------------------------------
+# Wall boundaries (Sec. IV C, IV D)
+# ---------------------------------------------------------------------------
+
+def _wall_run(walls, bc_x, steps, seed=4, shape=(9, 10), R=None):
+    g = np.random.default_rng(seed)
+    ny, nx = shape
+    F = dict(rho=1.0 + 0.2 * g.random(shape), ux=0.1 * g.standard_normal(shape),
+             uy=0.1 * g.standard_normal(shape), T=1.25 + 0.3 * g.random(shape), lam=np.zeros(shape))
+    w = W.detonation(nx=nx, ny=ny, steps=steps).with_(
+        Q=0.0, omega1=0.0, omega2=0.0, bc_x=bc_x, bc_y="outflow", walls=walls,
+        R=R or W.rates(100.0, r8=200.0, r9=150.0))
+    P, tab, f0, _ = oracle_init(w, fields=F)
+    _, _, f, _ = oracle_run(w, fields=F)
+    return om.moment_transform(f0, tab), om.moment_transform(f, tab)
+
+
+def test_reflecting_walls_conserve_mass_energy_and_tangential_momentum():
+    """A specular wall (ghost layers = the edge layers with mirrored velocities) passes no
+    mass, energy or tangential momentum: at the wall face the NND interface values of a
+    velocity and of its mirror are equal, so their fluxes cancel.  Reflecting walls at
+    both y sides with periodic x: sum rho, sum rho u_x and the total energy stay to
+    rounding over 40 steps (A_hat active), while sum rho u_y changes (wall pressure).
+    Zero-gradient outflow in their place loses mass."""
+    walls = {"y_lo": ("reflect",), "y_hi": ("reflect",)}
+    h0, h1 = _wall_run(walls, "periodic", 40)
+    for k in (0, 1, 3):
+        a, b = float(h0[k].sum()), float(h1[k].sum())
+        assert abs(a - b) < 1e-12 * float(h0[3].abs().sum()), k
+    assert abs(float(h1[2].sum() - h0[2].sum())) > 1e-6
+    o0, o1 = _wall_run(None, "periodic", 40)
+    assert abs(float(o1[0].sum() - o0[0].sum())) > 1e-6
+    # all four sides reflecting: mass and energy still conserved
+    walls4 = dict(walls, x_lo=("reflect",), x_hi=("reflect",))
+    h0, h1 = _wall_run(walls4, "outflow", 40)
+    for k in (0, 3):
+        assert abs(float(h0[k].sum() - h1[k].sum())) < 1e-12 * float(h0[3].abs().sum()), k
+
+
+def _uniform_fields(shape, rho, T, ux, uy):
+    z = np.zeros(shape)
+    return dict(rho=z + rho, ux=z + ux, uy=z + uy, T=z + T, lam=z + 0.25)
+
+
+def test_dirichlet_and_comoving_extrapolation_walls_keep_a_uniform_state():
+    """A Dirichlet side holding the interior state, and non-equilibrium-extrapolation walls
+    moving with a uniform flow at its temperature, leave that state unchanged."""
+    st = (1.1, 0.9, 0.3, -0.05)
+    shape = (6, 8)
+    for walls, bc_x in (({"x_lo": ("dirichlet", st[0], st[1], st[2], st[3], 0.25)}, "outflow"),
+                        ({"y_lo": ("nee", st[1], st[2], st[3]), "y_hi": ("nee", st[1], st[2], st[3])}, "periodic")):
+        w = W.detonation(nx=shape[1], ny=shape[0], steps=20).with_(
+            Q=0.0, omega1=0.0, omega2=0.0, bc_x=bc_x, bc_y="outflow", walls=walls,
+            R=W.rates(100.0, r8=200.0, r9=150.0))
+        F = _uniform_fields(shape, *st)
+        P, tab, f, lam = oracle_run(w, fields=F)
+        m = oracle.moments(f, lam, P, tab)
+        assert float((m["rho"] - st[0]).abs().max()) < 1e-12
+        assert float((m["T"] - st[1]).abs().max()) < 1e-12
+        assert float((m["ux"] - st[2]).abs().max()) < 1e-12 and float((m["uy"] - st[3]).abs().max()) < 1e-12
+
+
+def test_extrapolation_wall_first_step_transfers_the_half_range_flux():
+    """Fluid at rest in equilibrium under a non-equilibrium-extrapolation wall moving at
+    u_w: in the first step only the velocities entering from the ghost side change the
+    edge cell, by dt |v_y| (f^eq_i(u_w) - f^eq_i(0)) / dy each (upwind NND with constant
+    ghost layers), so the x-momentum gained is dt/dy times the half-range moment
+    sum_{v_y < 0} v_x |v_y| (f^eq(u_w) - f^eq(0)).  For the velocity set of the paper's
+    Couette runs this moment is negative: the wall drags the fluid backwards (a property of
+    the discrete equilibrium's negative weights, not of the wall's momentum)."""
+    dvm = (0.8, 1.2, 1.3, 1.0, 2.7, 0.8)
+    uw, dt, dy = 0.1, 1e-5, 1e-3
+    w = W.Workload(name="couette", nx=1, ny=6, dx=dy, dy=dy, dt=dt, steps=1, dvm=dvm, gamma=1.5, I=2.0,
+                   R=W.rates(5e4, r5=2e3, r6=2e3, r7=2e3, r8=1e4, r9=1e4), bc_x="periodic", bc_y="outflow",
+                   walls={"y_hi": ("nee", 1.0, uw, 0.0)},
+                   make_fields=lambda w: _uniform_fields((w.ny, w.nx), 1.0, 1.0, 0.0, 0.0))
+    P, tab, f, lam = oracle_run(w)
+    jx = om.moment_transform(f, tab)[1][:, 0]
+    one = torch.ones(1, dtype=T64)
+    feq = lambda u: (tab.Minv @ om.equilibrium_moments(one, u * one, 0 * one, one, P.I))[:, 0]
+    d = feq(uw) - feq(0.0)
+    half = float((tab.vx * tab.vy.abs() * d)[tab.vy < 0].sum())
+    assert abs(float(jx[-1]) - dt / dy * half) < 1e-12 + 1e-9 * abs(dt / dy * half)
+    assert float(jx[:-1].abs().max()) < 1e-14
+    assert half < 0
+
+
 def test_srt_step_equals_mrt_step_with_equal_rates():
     """Eq. SRT against Eq. MRT (Sec. V): with every R_k = 1/tau, M^-1 R (f_hat - f_hat^eq)
     = (f - M^-1 f_hat^eq)/tau and A_hat vanishes (R_8 = R_5, R_9 = R_7), so one SRT step
@@ -558,6 +645,25 @@ def test_exact_riemann_solution_satisfies_jump_conditions(left, right):
             assert abs(ps / rs ** g - p0 / r0 ** g) < 1e-10 * p0 / r0 ** g
             c0, cs = math.sqrt(g * p0 / r0), math.sqrt(g * ps / rs)
             assert abs((u0 - sgn * 2 * c0 / (g - 1)) - (us - sgn * 2 * cs / (g - 1))) < 1e-10
+
+
+def test_oblique_shock_relations_reproduce_the_papers_incident_shock():
+    """Sec. IV C: the incident shock at phi = 30 deg with M_1 = 2.3094, gamma = 1.5 turns the
+    inflow (1, p = 0.5, u = 2) by theta with tan theta = 0.173205 / 1.9 = 0.091161 into the
+    printed top state (rho, T, u) = (1.25, 0.56, (1.9, -0.173205)); Eqs. RR1, RR2 give the
+    same jumps.  The oblique-shock solver (theta-beta-M relation, weak root) must return
+    beta = 30 deg and that state from (M_1, theta) alone."""
+    g = 1.5
+    th = math.atan(0.173205 / 1.9)
+    assert abs(math.tan(th) - 0.091161) < 1e-6
+    s = physics.oblique_shock(1.0, 0.5, 2.0, g, th)
+    assert abs(math.degrees(s["beta"]) - 30.0) < 1e-3
+    assert abs(s["rho"] - 1.25) < 1e-5 and abs(s["p"] - 0.7) < 1e-5
+    assert abs(s["speed"] - math.hypot(1.9, 0.173205)) < 1e-5
+    M1, phi = 2.3094, math.radians(30.0)
+    sn2 = M1 * M1 * math.sin(phi) ** 2
+    assert abs((g + 1) * sn2 / (2 + (g - 1) * sn2) - 1.25) < 1e-5          # Eq. RR1
+    assert abs((2 * g * sn2 - (g - 1)) / (g + 1) - 1.4) < 1e-5             # Eq. RR2
 
 
 def test_sod_shock_tube_matches_exact_riemann_solution():
