@@ -16,9 +16,9 @@ model    : equilibrium moments, modification terms, chemistry, NND streaming,
            one forward-Euler time step, initialisation and the TNE readouts
            (Sec. II, Sec. VI).
 physics  : independent physics references used to pin the model: the exact
-           Riemann solution of the Euler equations, the Chapman-Jouguet and
-           von Neumann states, and Gauss-Hermite moments of the continuous
-           Maxwellian.
+           Riemann solution of the Euler equations, oblique-shock relations, the
+           Chapman-Jouguet and von Neumann states, and Gauss-Hermite moments of
+           the continuous Maxwellian.
 
 What pins each function (tests/test_oracle_pins.py, checked against the paper or
 the mathematics, never against the oracle itself):
@@ -35,6 +35,12 @@ the mathematics, never against the oracle itself):
   collision_srt         one SRT step with tau equals one MRT step with every R_k =
                         1/tau (A_hat then vanishes; an identity of Eqs. SRT and MRT);
                         closed-form decay (1 - dt/tau)^n of every component of f - f^eq
+  wall_layers, padded   reflecting walls pass no mass, energy or tangential momentum
+                        (exact flux cancellation at the wall face); Dirichlet and
+                        co-moving extrapolation walls keep a uniform state; the first
+                        step under a moving extrapolation wall transfers exactly the
+                        half-range flux of the equilibria; the shock-reflection states
+                        (physics.oblique_shock reproduces the paper's incident shock)
   modification_terms    its sign: only the chosen sign makes the viscous heating
                         independent of R_8 (Chapman-Enskog, Sec. III)
   cochran_increment     exact solution of the rate equation (against a fine RK4);
@@ -61,7 +67,7 @@ printed; a project choice of the workloads).
 from .dvm import DVM, velocity_set, moment_matrix, inverse_moment_matrix
 from .model import Params, Tables, make_tables, equilibrium_moments, macroscopic, \
     modification_terms, cochran_increment, chemical_term, nnd_derivative, \
-    collision, collision_srt, step, run, init_f, moments, tne, reductions
+    collision, collision_srt, step, run, init_f, moments, tne, reductions, wall_layers, padded
 
 __all__ = [
     "DVM", "velocity_set", "moment_matrix", "inverse_moment_matrix",
