@@ -5,6 +5,11 @@
 // NND streaming of all 24 planes, forward Euler, and the lambda update.  All inputs are
 // read at level n from `fin`/`lin`; results go to the other buffer pair.
 //
+// Compile-time specialisations (the host picks one per launch): A_hat possible, reaction
+// possible, general rate exponents; the single-relaxation-time collision of Eq. SRT; a
+// Runge-Kutta stage (the Euler update blended with f^n at the cell); wall sides (stencil
+// points beyond a wall read the ghost layers that k_ghost filled).
+//
 // Instruction economy (the kernel is issue-bound unless this is watched):
 //  - the 324 moment-matrix entries are read column by column with scalar loads and
 //    consumed at once (column-major matrix-vector products);
