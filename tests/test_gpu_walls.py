@@ -93,3 +93,16 @@ def test_shock_reflection_reaches_the_regular_reflection_state():
               f"u_x {ux:.4f} ({ux_e:.4f})  u_y {uy:.4f} ({uy_e:.4f})  cells {int(mask.sum())}", flush=True)
         assert abs(rho - rho_e) < 0.02 * rho_e and abs(p - p_e) < 0.02 * p_e, name
         assert abs(ux - ux_e) < 0.02 * ux_e and abs(uy - uy_e) < 0.02 * ux_e, name
+
+
+def test_walls_with_srt_collision_and_rk3():
+    """Wall sides together with the single-relaxation-time collision and SSP-RK3 (ghost
+    layers refilled for each of the three stages): reflecting bottom and top, Dirichlet
+    inflow at the left, outflow at the right; 24 x 20 cells, 40 steps."""
+    walls = {"y_lo": ("reflect",), "y_hi": ("reflect",), "x_lo": ("dirichlet", 1.05, 1.3, 0.1, 0.0, 0.2)}
+    w, F = _case(24, 20, walls, 40, rk=3)
+    w = w.with_(tau=1.0 / 100.0)
+    s, g = _gpu(w, w.steps, fields=F)
+    P, tab, f, lam = oracle_run(w, fields=F)
+    assert P.tau > 0 and P.rk == 3
+    _assert_parity(g, P, tab, f, lam, label="walls + SRT + RK3")
