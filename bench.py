@@ -8,11 +8,11 @@ the fused step kernel.  Reported beside it on the same GPU: the batched form (12
 1D detonations, one persistent launch per graph replay) and the adjoint form (gradient of
 the non-equilibrium loss over a 2048 x 256 detonation strip, 500 steps, checkpoints every
 50), each against the plain step's time per cell-update, and the reactive run with the
-single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I) and with the
-SSP Runge-Kutta time schemes.  Prints one JSON line.
+single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I), with the
+SSP Runge-Kutta time schemes, and between reflecting walls.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
-                  [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk]
+                  [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk] [--no-walls]
 """
 
 from __future__ import annotations
@@ -242,6 +242,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-srt", action="store_true")
     ap.add_argument("--no-rk", action="store_true")
+    ap.add_argument("--no-walls", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -300,6 +301,18 @@ def main():
             del s2
             torch.cuda.empty_cache()
 
+    walls = None
+    if not args.no_walls:
+        # the same reactive run between reflecting walls at both y sides (ghost layers filled
+        # before each step, the ghost-aware step specialisation)
+        ww = w.with_(bc_y="outflow", walls={"y_lo": ("reflect",), "y_hi": ("reflect",)})
+        s3 = lbkm.sim_from_workload(ww)
+        ms3 = time_steps(s3, args.steps, args.warmup)
+        walls = {"ms_per_step": round(ms3, 5), "mlups": round(cells / (ms3 * 1e-3) / 1e6, 2),
+                 "time_over_periodic": round(ms3 / ms, 4), "finite": bool(s3.check())}
+        del s3
+        torch.cuda.empty_cache()
+
     achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
     ceiling = copy_ceiling_gbs()
     traffic = measured_traffic()
@@ -328,6 +341,7 @@ def main():
         "inert_Q0": inert,
         "srt_collision": srt,
         "runge_kutta": schemes,
+        "reflecting_walls_y": walls,
     }
     ns_cell = ms * 1e6 / cells
     if not args.no_batched:

@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbkm_device.h"
 #include "lbkm_kernels.h"
 
@@ -178,43 +180,56 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 2: NND streaming plane by plane; the centre value is read again (a cache hit)
-    // so that only src[] stays live across the planes.
+    // so that only src[] stays live across the planes.  GH: stencil points may lie on wall
+    // ghost layers (instantiated only in the wall specialisation).
     const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
     const uint32_t pb = opaque(F.plane_bytes);
-    VelAcc va;                                  // velocity of the new state (for A_hat)
+    auto phase2 = [&](auto gh_on) {
+        constexpr bool GH = decltype(gh_on)::value;
+        VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double v = c->vg[g];
+        for (int g = 0; g < 3; ++g) {
+            const double v = c->vg[g];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const uint32_t so = (uint32_t)(8 * g + d) * pb;
-            const uint32_t sg = GHOST ? (uint32_t)(8 * g + d) * Gb.plane_bytes : 0u;
-            auto at = [&](uint32_t off, int k) { return sld<GHOST>(F, so, off, Gb, sg, gh, k); };
-            const double f0 = ld(F, so, s.c);
-            double adv = 0.0;
-            if (DUX[d] > 0) adv += v * (nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)) * idx_);
-            if (DUX[d] < 0) adv -= v * (nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)) * idx_);
-            if (DUY[d] > 0) adv += v * (nnd_pos(at(s.ym2, 4), at(s.ym1, 5), f0, at(s.yp1, 6)) * idy);
-            if (DUY[d] < 0) adv -= v * (nnd_neg(at(s.ym1, 5), f0, at(s.yp1, 6), at(s.yp2, 7)) * idy);
-            double out = f0 + dt * (src[8 * g + d] - adv);
-            if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
-            if (AMOD) vel_add(va, c, g, d, out);
-            st_stream(G, so, s.c, out);
+            for (int d = 0; d < 8; ++d) {
+                const uint32_t so = (uint32_t)(8 * g + d) * pb;
+                const uint32_t sg = GH ? (uint32_t)(8 * g + d) * Gb.plane_bytes : 0u;
+                auto at = [&](uint32_t off, int k) { return sld<GH>(F, so, off, Gb, sg, gh, k); };
+                const double f0 = ld(F, so, s.c);
+                double adv = 0.0;
+                if (DUX[d] > 0) adv += v * (nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)) * idx_);
+                if (DUX[d] < 0) adv -= v * (nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)) * idx_);
+                if (DUY[d] > 0) adv += v * (nnd_pos(at(s.ym2, 4), at(s.ym1, 5), f0, at(s.yp1, 6)) * idy);
+                if (DUY[d] < 0) adv -= v * (nnd_neg(at(s.ym1, 5), f0, at(s.yp1, 6), at(s.yp2, 7)) * idy);
+                double out = f0 + dt * (src[8 * g + d] - adv);
+                if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
+                if (AMOD) vel_add(va, c, g, d, out);
+                st_stream(G, so, s.c, out);
+            }
         }
+        if (AMOD) {
+            st_stream(Uo, 0u, s.c, va.jx / va.r);
+            st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
+        }
+        const uint32_t sl = GH ? NV * Gb.plane_bytes : 0u;
+        auto lat = [&](uint32_t off, int k) { return sld<GH>(L, 0u, off, Gb, sl, gh, k); };
+        const double dlx = (m.ux > 0.0) ? nnd_pos(lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2))
+                                        : nnd_neg(lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
+        const double dly = (m.uy > 0.0) ? nnd_pos(lat(s.ym2, 4), lat(s.ym1, 5), lam, lat(s.yp1, 6))
+                                        : nnd_neg(lat(s.ym1, 5), lam, lat(s.yp1, 6), lat(s.yp2, 7));
+        double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+        if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
+        st_stream(Lo, 0u, s.c, lnew);
+    };
+    if constexpr (GHOST) {
+        // only waves with a stencil point on a ghost layer take the selecting path
+        if (__ballot(gh.is != 0u) != 0ull)
+            phase2(std::true_type{});
+        else
+            phase2(std::false_type{});
+    } else {
+        phase2(std::false_type{});
     }
-    if (AMOD) {
-        st_stream(Uo, 0u, s.c, va.jx / va.r);
-        st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
-    }
-    const uint32_t sl = GHOST ? NV * Gb.plane_bytes : 0u;
-    auto lat = [&](uint32_t off, int k) { return sld<GHOST>(L, 0u, off, Gb, sl, gh, k); };
-    const double dlx = (m.ux > 0.0) ? nnd_pos(lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2))
-                                    : nnd_neg(lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
-    const double dly = (m.uy > 0.0) ? nnd_pos(lat(s.ym2, 4), lat(s.ym1, 5), lam, lat(s.yp1, 6))
-                                    : nnd_neg(lat(s.ym1, 5), lam, lat(s.yp1, 6), lat(s.yp2, 7));
-    double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
-    if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
-    st_stream(Lo, 0u, s.c, lnew);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -343,10 +358,11 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
 }
 
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
-// general: the reactive specialisations then fit without spilling and the compiler stops
-// parking scalar registers in vector lanes; the general-exponent ones would spill.
+// general, or walls meet A_hat and the reaction: the other specialisations then fit without
+// spilling, the compiler stops parking scalar registers in vector lanes, and the wall
+// specialisation's interior waves run as fast as the plain kernel; those two would spill.
 template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND, bool GHOST>
-__global__ __launch_bounds__(TX * TY, (GEXP || GHOST) ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
+__global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3) void k_step(const Consts* __restrict__ c, const double* __restrict__ fin,
                                                   double* __restrict__ fout, const double* __restrict__ lin,
                                                   double* __restrict__ lout, const double* __restrict__ uin,
                                                   double* __restrict__ uout, int gx, int ntiles, int vertical,
