@@ -110,7 +110,14 @@ lbkm_status lbkm_set_params(lbkm_ctx* ctx, const double S[24], double gamma, dou
 lbkm_status lbkm_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
                              const double* uy, const double* T, const double* lambda);
 
-/* Advance n >= 0 time steps (asynchronous). */
+/* Advance n >= 0 time steps on the bound stream (asynchronous).  One step is one launch
+ * of the fused step kernel (forward Euler, Eq. Boltzmann_chemical with the readings of the
+ * library), or 2 / 3 launches for the Runge-Kutta schemes of lbkm_set_time_scheme; with
+ * wall sides (lbkm_set_boundary) each launch is preceded by the fill of the ghost layers.
+ * The library allocates, on first need and for the life of the context, the velocity planes
+ * of the modification term, the third Runge-Kutta state and the ghost layers.  Errors:
+ * EINVAL for n < 0; ESTATE before buffers, parameters and fields are set; EDEVICE for a
+ * failed launch or allocation. */
 lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n);
 
 /* Macroscopic readout rho, u_x, u_y, T, p = rho T, lambda into dense [ny][nx]
@@ -197,8 +204,9 @@ lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order);
 /* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
  * orders for a few steps from the current state, keeps the fastest, and restores the
  * state and the step count (the trial steps run on the bound buffers; a temporary copy
- * of the state is allocated).  Needs parameters and fields.  choice (host, 4 ints, may
- * be NULL) receives tile_x, tile_y, lds, vertical.  Synchronous. */
+ * of the state is allocated).  With wall sides there is one shape (256 x 2, direct) and
+ * nothing is timed.  Needs parameters and fields.  choice (host, 4 ints, may be NULL)
+ * receives tile_x, tile_y, lds, vertical.  Synchronous. */
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice);
 
 /* Host copies of the dense 24x24 moment matrix M (row k = moment m_{k+1}, column i =
