@@ -120,10 +120,26 @@ def cpu_baseline(w, tile=1024, steps=8):
     t0 = time.perf_counter()
     f, lam = oracle.run(f, lam, P, tab, steps)
     dt = time.perf_counter() - t0
+    cores = torch.get_num_threads()
+    # the same oracle on one thread, on a 256^2 corner of the cut for 4 steps
+    small = 256
+    f1 = oracle.init_f(*(t[k][:small, :small].contiguous() for k in ("rho", "ux", "uy", "T")), P, tab)
+    l1 = t["lam"][:small, :small].contiguous()
+    torch.set_num_threads(1)
+    try:
+        f1, l1 = oracle.step(f1, l1, P, tab)
+        t1 = time.perf_counter()
+        f1, l1 = oracle.run(f1, l1, P, tab, 4)
+        dt1 = time.perf_counter() - t1
+    finally:
+        torch.set_num_threads(cores)
     return {"value": round(tile * tile * steps / dt / 1e6, 4), "unit": "MLUPS",
-            "cores": torch.get_num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{tile}x{tile} periodic cut of the 2048^2 KH initial fields (reactive), "
-                      f"{steps} steps after 1 untimed step, {dt:.1f} s"}
+                      f"{steps} steps after 1 untimed step, {dt:.1f} s",
+            "one_thread_value": round(small * small * 4 / dt1 / 1e6, 4),
+            "one_thread_sample": f"{small}x{small} corner of the same cut, 4 steps after 1 untimed step, "
+                                 f"{dt1:.1f} s"}
 
 
 def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
