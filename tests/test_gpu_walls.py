@@ -69,21 +69,26 @@ def test_shock_reflection_reaches_the_regular_reflection_state():
     0.173205 / 1.9).  Sampled away from the shocks: the inflow region, the region between
     the shocks, and the reflected region next to the wall."""
     from oracle import physics
+    from tests.test_oracle_pins import _golden
+    gd = _golden("shock_reflection.txt")
     w = W.shock_reflection()
     s, g = _gpu(w, w.steps)
     assert s.check()
     x = (np.arange(w.nx) + 0.5) * w.dx
     y = (np.arange(w.ny) + 0.5) * w.dy
     X, Y = np.meshgrid(x, y)
-    gam = 1.5
-    th = math.atan(0.173205 / 1.9)
-    r3 = physics.oblique_shock(1.25, 0.7, math.hypot(1.9, 0.173205), gam, th)
-    xr = 0.1 / math.tan(math.radians(30.0))
+    gam = gd["gamma"]
+    th = math.atan(-gd["uy2"] / gd["ux2"])
+    rho2, p2 = gd["rho2"], gd["rho2"] * gd["T2"]
+    r3 = physics.oblique_shock(rho2, p2, math.hypot(gd["ux2"], gd["uy2"]), gam, th)
+    phi = math.radians(gd["phi_deg"])
+    xr = 0.1 / math.tan(phi)
     h3 = lambda xx: (xx - xr) * math.tan(r3["beta"] - th)          # reflected shock height
     regions = {
-        "1": ((X > 0.02) & (X < 0.06) & (Y < 0.1 - X * math.tan(math.radians(30.0)) - 0.02), (1.0, 0.5, 2.0, 0.0)),
-        "2": ((X > 0.12) & (X < 0.16) & (Y > 0.1 - X * math.tan(math.radians(30.0)) + 0.015) & (Y < 0.09),
-              (1.25, 0.7, 1.9, -0.173205)),
+        "1": ((X > 0.02) & (X < 0.06) & (Y < 0.1 - X * math.tan(phi) - 0.02),
+              (gd["rho1"], gd["rho1"] * gd["T1"], gd["ux1"], 0.0)),
+        "2": ((X > 0.12) & (X < 0.16) & (Y > 0.1 - X * math.tan(phi) + 0.015) & (Y < 0.09),
+              (rho2, p2, gd["ux2"], gd["uy2"])),
         "3": ((X > 0.23) & (X < 0.27) & (Y > 0.003) & (Y < 0.6 * h3(0.23)), (r3["rho"], r3["p"], r3["speed"], 0.0)),
     }
     for name, (mask, (rho_e, p_e, ux_e, uy_e)) in regions.items():

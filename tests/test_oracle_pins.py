@@ -648,22 +648,25 @@ def test_exact_riemann_solution_satisfies_jump_conditions(left, right):
 
 
 def test_oblique_shock_relations_reproduce_the_papers_incident_shock():
-    """Sec. IV C: the incident shock at phi = 30 deg with M_1 = 2.3094, gamma = 1.5 turns the
-    inflow (1, p = 0.5, u = 2) by theta with tan theta = 0.173205 / 1.9 = 0.091161 into the
-    printed top state (rho, T, u) = (1.25, 0.56, (1.9, -0.173205)); Eqs. RR1, RR2 give the
-    same jumps.  The oblique-shock solver (theta-beta-M relation, weak root) must return
-    beta = 30 deg and that state from (M_1, theta) alone."""
-    g = 1.5
-    th = math.atan(0.173205 / 1.9)
-    assert abs(math.tan(th) - 0.091161) < 1e-6
-    s = physics.oblique_shock(1.0, 0.5, 2.0, g, th)
-    assert abs(math.degrees(s["beta"]) - 30.0) < 1e-3
-    assert abs(s["rho"] - 1.25) < 1e-5 and abs(s["p"] - 0.7) < 1e-5
-    assert abs(s["speed"] - math.hypot(1.9, 0.173205)) < 1e-5
-    M1, phi = 2.3094, math.radians(30.0)
+    """Sec. IV C (values in tests/golden/shock_reflection.txt): the incident shock at phi with
+    Mach number M_1 turns the inflow state by theta, tan theta = 0.173205 / 1.9 = 0.091161,
+    into the printed top state; Eqs. RR1, RR2 give the same jumps.  The oblique-shock
+    solver (theta-beta-M relation, weak root) must return beta = phi and that state from
+    the inflow and theta alone."""
+    gd = _golden("shock_reflection.txt")
+    g = gd["gamma"]
+    th = math.atan(-gd["uy2"] / gd["ux2"])
+    assert abs(math.tan(th) - gd["tan_theta"]) < 1e-6
+    p1, p2 = gd["rho1"] * gd["T1"], gd["rho2"] * gd["T2"]
+    s = physics.oblique_shock(gd["rho1"], p1, gd["ux1"], g, th)
+    assert abs(math.degrees(s["beta"]) - gd["phi_deg"]) < 1e-3
+    assert abs(s["rho"] - gd["rho2"]) < 1e-5 and abs(s["p"] - p2) < 1e-5
+    assert abs(s["speed"] - math.hypot(gd["ux2"], gd["uy2"])) < 1e-5
+    assert abs(gd["ux1"] / math.sqrt(g * gd["T1"]) - gd["M1"]) < 1e-4     # M_1 of the inflow
+    M1, phi = gd["M1"], math.radians(gd["phi_deg"])
     sn2 = M1 * M1 * math.sin(phi) ** 2
-    assert abs((g + 1) * sn2 / (2 + (g - 1) * sn2) - 1.25) < 1e-5          # Eq. RR1
-    assert abs((2 * g * sn2 - (g - 1)) / (g + 1) - 1.4) < 1e-5             # Eq. RR2
+    assert abs((g + 1) * sn2 / (2 + (g - 1) * sn2) - gd["rho2"] / gd["rho1"]) < 1e-5   # Eq. RR1
+    assert abs((2 * g * sn2 - (g - 1)) / (g + 1) - p2 / p1) < 1e-5                     # Eq. RR2
 
 
 def test_sod_shock_tube_matches_exact_riemann_solution():
