@@ -85,12 +85,17 @@ typedef struct { double omega1, omega2, m, n, T_ig; } lbkm_rates;
  * builds M and its block inverse on the host (LBKM_ESINGULAR if M is singular
  * or its condition number exceeds 1e12).  hip_stream is a hipStream_t or NULL.
  * No device work happens here (device tables are allocated by lbkm_bind_buffers).
+ * The kernels address the 24 planes of one state with 32-bit byte offsets, so
+ * 24 * nx * ny doubles must stay within 4 GiB (about 22.3 million cells; a larger
+ * domain is split into several grids): LBKM_EINVAL otherwise.
  * On failure *out may still hold a context for lbkm_last_error; destroy it. */
 lbkm_status lbkm_create(const lbkm_grid* grid, void* hip_stream, lbkm_ctx** out);
 
 /* Bind caller-owned device buffers: f_a, f_b of 24*ny*pitch doubles and
  * lam_a, lam_b of ny*pitch doubles (pitch >= nx elements).  The state lives in
- * the "a" buffers after init_fields/set_state and ping-pongs between a and b. */
+ * the "a" buffers after init_fields/set_state and ping-pongs between a and b.
+ * LBKM_EINVAL for NULL or equal buffers, pitch < nx, or 24*ny*pitch doubles
+ * beyond 4 GiB (checked before any device work). */
 lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b,
                               double* lam_a, double* lam_b, int64_t pitch);
 
@@ -184,8 +189,9 @@ lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau);
  * state: host array of 5 doubles (used by types 2 and 3; may be NULL for 0 and 1).  A wall
  * needs bc = LBKM_BC_OUTFLOW on its axis (the opposite side keeps that rule unless it is a
  * wall too).  With a wall the step uses the 256 x 2 direct launch shape.  Errors: EINVAL
- * for a bad side, type, axis rule or state (non-finite, rho <= 0 or T <= 0); ESTATE on a
- * batched context.  lbkm_adjoint_step refuses a context with walls (ESTATE). */
+ * for a bad side, type, axis rule or state (non-finite, rho <= 0 or T <= 0), or when the
+ * library-owned ghost layers (27 * 8 * max(nx, ny) doubles) would exceed 4 GiB; ESTATE on
+ * a batched context.  lbkm_adjoint_step refuses a context with walls (ESTATE). */
 lbkm_status lbkm_set_boundary(lbkm_ctx* ctx, int32_t side, int32_t type, const double* state);
 
 /* Time integration of the single-grid step.  order = 1: forward Euler (the default, the

@@ -154,6 +154,8 @@ lbkm_status lbkm_create(const lbkm_grid* grid, void* hip_stream, lbkm_ctx** out)
     ctx->grid = *grid;
     lbkm_status st = LBKM_OK;
     if (grid->nx < 1 || grid->ny < 1) st = fail(ctx, LBKM_EINVAL, "nx and ny must be >= 1");
+    if (st == LBKM_OK && (int64_t)NV * grid->nx * grid->ny * 8 > 0xFFFFFFFFll)
+        st = fail(ctx, LBKM_EINVAL, "24 nx ny doubles exceed 4 GiB (the kernels use 32-bit plane offsets)");
     if (st == LBKM_OK && ((grid->bc_x != LBKM_BC_PERIODIC && grid->bc_x != LBKM_BC_OUTFLOW) ||
                           (grid->bc_y != LBKM_BC_PERIODIC && grid->bc_y != LBKM_BC_OUTFLOW)))
         st = fail(ctx, LBKM_EINVAL, "unknown boundary condition");
@@ -175,6 +177,8 @@ lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b, double* l
     if (!f_a || !f_b || !lam_a || !lam_b) return fail(ctx, LBKM_EINVAL, "NULL buffer");
     if (f_a == f_b || lam_a == lam_b) return fail(ctx, LBKM_EINVAL, "the two buffers of a pair must differ");
     if (pitch < ctx->grid.nx) return fail(ctx, LBKM_EINVAL, "pitch < nx");
+    if ((int64_t)NV * pitch * ctx->grid.ny * 8 > 0xFFFFFFFFll)
+        return fail(ctx, LBKM_EINVAL, "24 pitch ny doubles exceed 4 GiB (the kernels use 32-bit plane offsets)");
     ctx->f[0] = f_a;
     ctx->f[1] = f_b;
     ctx->lam[0] = lam_a;
@@ -444,6 +448,8 @@ lbkm_status lbkm_set_boundary(lbkm_ctx* ctx, int32_t side, int32_t type, const d
     const int axis_bc = side < 2 ? ctx->grid.bc_x : ctx->grid.bc_y;
     if (type != kWallNone && axis_bc != LBKM_BC_OUTFLOW)
         return fail(ctx, LBKM_EINVAL, "a wall side needs the outflow rule on its axis (the other side keeps it)");
+    if (type != kWallNone && (int64_t)kGhostPlanes * 8 * ctx->h.gL * 8 > 0xFFFFFFFFll)
+        return fail(ctx, LBKM_EINVAL, "ghost layers beyond 4 GiB (the longer grid side is too long for walls)");
     double v[5] = {0, 0, 0, 0, 0};
     if (type == kWallDirichlet || type == kWallNee) {
         if (!state) return fail(ctx, LBKM_EINVAL, "this boundary type needs a state");

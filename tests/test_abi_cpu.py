@@ -56,6 +56,7 @@ def _destroy(h):
                                        ({"dt": 0.0}, -1), ({"bcx": 7}, -1),
                                        ({"dvm": (2.0, 2.0, 1.2, 1.0, 1.0, 0.5)}, -2),
                                        ({"dvm": (2.0, 1.0, 1.2, -1.0, 2.0, 0.5)}, -1),
+                                       ({"nx": 4730, "ny": 4730}, -1), ({"nx": 4729, "ny": 4729}, 0),
                                        ({}, 0)])
 def test_create_validates_grid(kw, status):
     st, h, msg = _create(_grid(**kw))
@@ -130,6 +131,34 @@ def test_set_boundary_validates(side, typ, state, status):
         arr = None if state is None else (ctypes.c_double * 5)(*state)
         st = L.load().lbkm_set_boundary(h, side, typ, arr)
         assert st == status, L.load().lbkm_last_error(h).decode()
+    finally:
+        _destroy(h)
+
+
+def test_bind_buffers_rejects_a_pitch_beyond_32_bit_plane_offsets():
+    """The planes of one state are addressed with 32-bit byte offsets: 24 * ny * pitch
+    doubles must stay within 4 GiB.  The check comes before any device work."""
+    lib = L.load()
+    st, h, msg = _create(_grid())
+    try:
+        assert st == 0, msg
+        ny = _grid().ny
+        pitch = (0xFFFFFFFF // (24 * 8 * ny)) + 1
+        assert lib.lbkm_bind_buffers(h, 1, 2, 3, 4, ctypes.c_int64(pitch)) == -1
+        assert "4 GiB" in lib.lbkm_last_error(h).decode()
+        assert lib.lbkm_bind_buffers(h, 1, 2, 3, 4, ctypes.c_int64(3)) == -1   # pitch < nx
+    finally:
+        _destroy(h)
+
+
+def test_walls_on_a_grid_too_long_for_the_ghost_layers_are_rejected():
+    """27 planes x 4 sides x 2 layers x max(nx, ny) ghost doubles must stay within 4 GiB."""
+    lib = L.load()
+    st, h, msg = _create(_grid(nx=2_500_000, ny=1, bcx=1, bcy=1))
+    try:
+        assert st == 0, msg
+        assert lib.lbkm_set_boundary(h, 0, 1, None) == -1
+        assert "4 GiB" in lib.lbkm_last_error(h).decode()
     finally:
         _destroy(h)
 
