@@ -53,7 +53,10 @@ the mathematics, never against the oracle itself):
   step, run, init_f     Sod (I = 3), Lax (I = 1) and Sjogren (I = 4) against the exact
                         Riemann solutions; the CJ plateau of a
                         detonation; shear-wave decay at the Chapman-Enskog
-                        viscosity; conservation on periodic grids
+                        viscosity; the relaxed heat-flux moment Delta_8 of a
+                        temperature wave equals -2 kappa dT/dx with the conductivity
+                        of Sec. III (pins R_8/R_9, c_p and f_hat^eq rows 8 and 14);
+                        conservation on periodic grids
   tne, reductions       readout identities (Sec. VI)
   (reverse-mode AD)     the gradient of a run agrees with central differences of
                         the oracle's forward run

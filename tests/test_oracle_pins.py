@@ -768,6 +768,39 @@ def test_shear_wave_decays_at_the_chapman_enskog_viscosity():
     assert abs((0.01 - amp) / (0.01 - half) - 1) > 0.5
 
 
+@pytest.mark.parametrize("Rmu,Rk,I", [(2000.0, 1000.0, 3.0), (1000.0, 2000.0, 3.0), (1000.0, 1000.0, 2.0)])
+def test_heat_flux_nonequilibrium_is_the_chapman_enskog_conduction(Rmu, Rk, I):
+    """Sec. III: with R_8 = R_9 = R_kappa the heat conductivity is kappa = c_p rho T / R_kappa,
+    c_p = (D+I+2)/2, independently of R_mu = R_5 = R_6 = R_7 (Pr = R_kappa / R_mu).  Moment 8
+    is sum f (v^2+eta^2) v_x, twice the energy flux, so once the flux has relaxed (ten times
+    1/R_kappa) its non-equilibrium part is twice Fourier's flux: Delta_8 = -2 kappa dT/dx =
+    -(D+I+2) p dT/dx / R_kappa.  The state is a temperature wave at uniform pressure and rest.
+    A wrong rate index for the heat-flux moments, a wrong c_p or a wrong entry 8 or 14 of
+    f_hat^eq moves the ratio by 15 % or more."""
+    D = 2.0
+    nx, kw, T0, eps, dt, n = 64, 1, 2.5, 1e-3, 1e-4, 100
+    P = _params(I=I, R=W.rates(1e4, r5=Rmu, r6=Rmu, r7=Rmu, r8=Rk, r9=Rk), dx=1.0 / nx, dy=1.0 / nx, dt=dt,
+                bc_x="periodic", bc_y="periodic")
+    tab = om.make_tables(P)
+    x = (np.arange(nx) + 0.5) / nx
+    s, co = np.sin(2 * np.pi * kw * x), np.cos(2 * np.pi * kw * x)
+    one = torch.ones(1, nx, dtype=T64)
+    rho = torch.from_numpy(1 + eps * s)[None, :]
+    f = om.init_f(rho, 0 * one, 0 * one, T0 / rho, P, tab)
+    f, lam = om.run(f, 0 * one, P, tab, n)
+    m = om.moments(f, lam, P, tab)
+    delta, _ = om.tne(f, P, tab)
+    T, p = m["T"][0].numpy(), m["p"][0].numpy()
+    a, b = 2 * np.mean((T - T.mean()) * s), 2 * np.mean((T - T.mean()) * co)
+    dTdx = 2 * np.pi * kw * (a * co - b * s)           # derivative of the wave's fundamental
+    want = -(D + I + 2) * p * dTdx / Rk
+    got = delta[3][0].numpy()                            # Delta_8
+    ratio = float(np.sum(got * want) / np.sum(want * want))
+    assert abs(ratio - 1.0) < 0.01
+    assert np.max(np.abs(got - want)) < 0.06 * np.max(np.abs(want))
+    assert float(delta[4].abs().max()) < 1e-6 * np.max(np.abs(want))   # no flux across the wave
+
+
 @pytest.mark.slow
 def test_detonation_plateau_is_the_cj_state():
     """Steady detonation of Sec. IV A, coarsened (dx = 5e-4, dt = 1e-5, x in [0, 0.5], t = 0.1
