@@ -56,6 +56,8 @@ the mathematics, never against the oracle itself):
                         viscosity; the relaxed heat-flux moment Delta_8 of a
                         temperature wave equals -2 kappa dT/dx with the conductivity
                         of Sec. III (pins R_8/R_9, c_p and f_hat^eq rows 8 and 14);
+                        the relaxed normal stresses Delta_5, Delta_7 of a longitudinal
+                        wave equal the Chapman-Enskog stresses for I = 1, 3, 4;
                         conservation on periodic grids
   tne, reductions       readout identities (Sec. VI)
   (reverse-mode AD)     the gradient of a run agrees with central differences of

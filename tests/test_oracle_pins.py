@@ -801,6 +801,42 @@ def test_heat_flux_nonequilibrium_is_the_chapman_enskog_conduction(Rmu, Rk, I):
     assert float(delta[4].abs().max()) < 1e-6 * np.max(np.abs(want))   # no flux across the wave
 
 
+@pytest.mark.parametrize("Rmu,Rk,I", [(2000.0, 1000.0, 3.0), (1000.0, 2000.0, 3.0), (1000.0, 1000.0, 1.0),
+                                      (1000.0, 1000.0, 4.0)])
+def test_normal_stress_nonequilibrium_is_the_chapman_enskog_stress(Rmu, Rk, I):
+    """Sec. III: mu = rho T / R_mu with R_5 = R_6 = R_7 = R_mu, and the I extra degrees of freedom
+    enter through gamma = (D+I+2)/(D+I).  For a longitudinal wave u_x(x) at uniform rho, T, once
+    the stress has relaxed, first-order Chapman-Enskog on moments 5 and 7 (sums of f v_x^2 and
+    f v_y^2, whose fluxes are entries 10 and 12 of f_hat^eq and whose equilibria change at the
+    adiabatic rate dp/dt = -gamma p du_x/dx) gives Delta_5 = -(3 - gamma) p du_x/dx / R_mu and
+    Delta_7 = -Delta_5 / (D+I-1).  Independent of R_kappa.  A wrong stress rate index, a wrong
+    I in f_hat^eq or a wrong entry 10 or 12 fails one of the three checks."""
+    D = 2.0
+    nx, kw, T0, U, dt, n = 64, 1, 2.5, 1e-3, 1e-4, 100
+    P = _params(I=I, R=W.rates(1e4, r5=Rmu, r6=Rmu, r7=Rmu, r8=Rk, r9=Rk), dx=1.0 / nx, dy=1.0 / nx, dt=dt,
+                bc_x="periodic", bc_y="periodic")
+    tab = om.make_tables(P)
+    x = (np.arange(nx) + 0.5) / nx
+    s, co = np.sin(2 * np.pi * kw * x), np.cos(2 * np.pi * kw * x)
+    one = torch.ones(1, nx, dtype=T64)
+    f = om.init_f(one, torch.from_numpy(U * s)[None, :], 0 * one, T0 * one, P, tab)
+    f, lam = om.run(f, 0 * one, P, tab, n)
+    m = om.moments(f, lam, P, tab)
+    delta, _ = om.tne(f, P, tab)
+    u, p = m["ux"][0].numpy(), m["p"][0].numpy()
+    a, b = 2 * np.mean(u * s), 2 * np.mean(u * co)
+    dudx = 2 * np.pi * kw * (a * co - b * s)            # derivative of the wave's fundamental
+    gam = (D + I + 2) / (D + I)
+    want = -(3 - gam) * p * dudx / Rmu
+    got = delta[0][0].numpy()                            # Delta_5
+    ratio = float(np.sum(got * want) / np.sum(want * want))
+    assert abs(ratio - 1.0) < 0.01
+    assert np.max(np.abs(got - want)) < 0.06 * np.max(np.abs(want))
+    d7 = delta[2][0].numpy()                             # Delta_7
+    r7 = float(np.sum(d7 * got) / np.sum(got * got))
+    assert abs(r7 * (D + I - 1) + 1.0) < 0.01
+
+
 @pytest.mark.slow
 def test_detonation_plateau_is_the_cj_state():
     """Steady detonation of Sec. IV A, coarsened (dx = 5e-4, dt = 1e-5, x in [0, 0.5], t = 0.1
