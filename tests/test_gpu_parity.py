@@ -412,3 +412,46 @@ def test_check_flags_nonfinite_and_nonpositive_states():
     assert not s.check()
     s.set_state(f, lam)
     assert s.check()
+
+
+@pytest.mark.parametrize("wave,I", [("temperature", 3.0), ("temperature", 2.0), ("longitudinal", 1.0),
+                                    ("longitudinal", 4.0)])
+def test_gpu_tne_carries_the_chapman_enskog_fluxes(wave, I):
+    """The TNE readout of the HIP path after ten relaxation times of a small wave on a periodic
+    64 x 4 grid (Sec. III): a temperature wave at uniform pressure carries the heat flux
+    Delta_8 = -(D+I+2) p dT/dx / R_kappa; a longitudinal velocity wave carries the normal
+    stress Delta_5 = -(3 - gamma) p du_x/dx / R_mu and Delta_7 = -Delta_5 / (D+I-1).
+    Pr = R_kappa / R_mu = 0.5, so swapping the two rate groups moves either by a factor 2."""
+    from paper_1411_6697_amd import lbkm
+    D, nx, ny, T0, eps, dt, n, Rmu, Rk = 2.0, 64, 4, 2.5, 1e-3, 1e-4, 100, 2000.0, 1000.0
+    gam = (D + I + 2) / (D + I)
+    s = lbkm.Sim(nx, ny, 1.0 / nx, 1.0 / nx, dt, W.DVM_UNSTEADY_DET, bc_x="periodic", bc_y="periodic")
+    s.set_params(W.rates(1e4, r5=Rmu, r6=Rmu, r7=Rmu, r8=Rk, r9=Rk), gam)
+    x = (np.arange(nx) + 0.5) / nx
+    sn, co = np.sin(2 * np.pi * x), np.cos(2 * np.pi * x)
+    row = lambda v: np.tile(v, (ny, 1))
+    one = np.ones((ny, nx))
+    if wave == "temperature":
+        rho = row(1 + eps * sn)
+        s.init_fields(rho, 0 * one, 0 * one, T0 / rho, 0 * one)
+    else:
+        s.init_fields(one, row(eps * sn), 0 * one, T0 * one, 0 * one)
+    s.step(n)
+    m = {k: v.cpu().numpy() for k, v in s.moments().items()}
+    delta = s.tne()[0].cpu().numpy()
+    q = m["T"] if wave == "temperature" else m["ux"]
+    assert np.abs(q - q[:1]).max() <= 1e-12 * np.abs(q).max()          # rows stay identical
+    q, p = q[0], m["p"][0]
+    a, b = 2 * np.mean((q - q.mean()) * sn), 2 * np.mean((q - q.mean()) * co)
+    dq = 2 * np.pi * (a * co - b * sn)
+    if wave == "temperature":
+        want, got = -(D + I + 2) * p * dq / Rk, delta[3][0]
+    else:
+        want, got = -(3 - gam) * p * dq / Rmu, delta[0][0]
+    ratio = float(np.sum(got * want) / np.sum(want * want))
+    print(wave, I, "ratio", ratio, flush=True)
+    assert abs(ratio - 1.0) < 0.01
+    assert np.max(np.abs(got - want)) < 0.06 * np.max(np.abs(want))
+    if wave == "longitudinal":
+        r7 = float(np.sum(delta[2][0] * got) / np.sum(got * got))
+        assert abs(r7 * (D + I - 1) + 1.0) < 0.01
