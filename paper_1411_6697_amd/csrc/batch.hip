@@ -127,14 +127,14 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const double v = c->vg[g];
+        const double wx = dt * v * idx_;              // Courant number of the group
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const uint32_t so = (uint32_t)(8 * g + d) * pb;
             const double f0 = ld(F, so, oc);
-            double adv = 0.0;
-            if (DUX[d] > 0) adv += v * (nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)) * idx_);
-            if (DUX[d] < 0) adv -= v * (nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)) * idx_);
-            const double out = f0 + dt * (src[8 * g + d] - adv);
+            double out = fma(dt, src[8 * g + d], f0);
+            if (DUX[d] > 0) out = fma(-wx, nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)), out);
+            if (DUX[d] < 0) out = fma(wx, nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)), out);
             if (AMOD) vel_add(va, c, g, d, out);
             st(G, so, oc, out);
         }

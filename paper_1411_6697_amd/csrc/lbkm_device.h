@@ -204,15 +204,15 @@ __device__ __forceinline__ double minmod(double a, double b) {
 
 // NND differences h_{j+1/2} - h_{j-1/2} (to be divided by the spacing), Zhang 1988,
 // flux-split minmod form.  Positive speed uses j-2..j+1, negative speed j-1..j+2.
+// With h_{j+1/2} = f_j + mm(f_j - f_{j-1}, f_{j+1} - f_j)/2 and its neighbour, the
+// difference is the centred jump plus half the change of the limited slopes.
 __device__ __forceinline__ double nnd_pos(double fm2, double fm1, double f0, double fp1) {
-    const double hp = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);
-    const double hm = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);
-    return hp - hm;
+    const double d = f0 - fm1;
+    return fma(0.5, minmod(d, fp1 - f0) - minmod(fm1 - fm2, d), d);
 }
 __device__ __forceinline__ double nnd_neg(double fm1, double f0, double fp1, double fp2) {
-    const double hp = fp1 - 0.5 * minmod(fp1 - f0, fp2 - fp1);
-    const double hm = f0 - 0.5 * minmod(f0 - fm1, fp1 - f0);
-    return hp - hm;
+    const double d = fp1 - f0;
+    return fma(-0.5, minmod(d, fp2 - fp1) - minmod(f0 - fm1, d), d);
 }
 
 // Cochran increment of lambda over one step, p frozen (exact solution of the Bernoulli

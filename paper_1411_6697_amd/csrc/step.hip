@@ -190,18 +190,18 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
             const double v = c->vg[g];
+            const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const uint32_t so = (uint32_t)(8 * g + d) * pb;
                 const uint32_t sg = GH ? (uint32_t)(8 * g + d) * Gb.plane_bytes : 0u;
                 auto at = [&](uint32_t off, int k) { return sld<GH>(F, so, off, Gb, sg, gh, k); };
                 const double f0 = ld(F, so, s.c);
-                double adv = 0.0;
-                if (DUX[d] > 0) adv += v * (nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)) * idx_);
-                if (DUX[d] < 0) adv -= v * (nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)) * idx_);
-                if (DUY[d] > 0) adv += v * (nnd_pos(at(s.ym2, 4), at(s.ym1, 5), f0, at(s.yp1, 6)) * idy);
-                if (DUY[d] < 0) adv -= v * (nnd_neg(at(s.ym1, 5), f0, at(s.yp1, 6), at(s.yp2, 7)) * idy);
-                double out = f0 + dt * (src[8 * g + d] - adv);
+                double out = fma(dt, src[8 * g + d], f0);
+                if (DUX[d] > 0) out = fma(-wx, nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)), out);
+                if (DUX[d] < 0) out = fma(wx, nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)), out);
+                if (DUY[d] > 0) out = fma(-wy, nnd_pos(at(s.ym2, 4), at(s.ym1, 5), f0, at(s.yp1, 6)), out);
+                if (DUY[d] < 0) out = fma(wy, nnd_neg(at(s.ym1, 5), f0, at(s.yp1, 6), at(s.yp2, 7)), out);
                 if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
                 if (AMOD) vel_add(va, c, g, d, out);
                 st_stream(G, so, s.c, out);
@@ -313,12 +313,12 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
         if (i < NV) {
             const int g = i / 8, d = i % 8;
             const double v = c->vg[g];
-            double adv = 0.0;
-            if (DUX[d] > 0) adv += v * (nnd_pos(q[-2], q[-1], f0, q[1]) * idx_);
-            if (DUX[d] < 0) adv -= v * (nnd_neg(q[-1], f0, q[1], q[2]) * idx_);
-            if (DUY[d] > 0) adv += v * (nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]) * idy);
-            if (DUY[d] < 0) adv -= v * (nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]) * idy);
-            double out = f0 + dt * (src[i] - adv);
+            const double wx = dt * v * idx_, wy = dt * v * idy;
+            double out = fma(dt, src[i], f0);
+            if (DUX[d] > 0) out = fma(-wx, nnd_pos(q[-2], q[-1], f0, q[1]), out);
+            if (DUX[d] < 0) out = fma(wx, nnd_neg(q[-1], f0, q[1], q[2]), out);
+            if (DUY[d] > 0) out = fma(-wy, nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW]), out);
+            if (DUY[d] < 0) out = fma(wy, nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]), out);
             if (BLEND && inside) out = fma(bl.a, ld(Fn, (uint32_t)i * pb, out_off), bl.b * out);
             if (AMOD) vel_add(va, c, g, d, out);
             if (inside) st_stream(G, (uint32_t)i * pb, out_off, out);
