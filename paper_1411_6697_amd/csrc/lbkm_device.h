@@ -244,16 +244,28 @@ __device__ __forceinline__ void add_chemical(const Consts* __restrict__ c, const
                                              const double feq[NV], double src[NV]) {
     const double F = dlam / c->dt;
     const double common = c->Q * F / (c->I * c->DI * m.T * m.T);
-    const double base = -(1.0 + 2.0) * c->I * m.T;
+    // The bracket -(1+D) I T + I |v_i - u|^2 + eta_i^2, already times `common`, split into a
+    // part fixed by the group and |v_i| and a part linear in v_i:
+    //   common [I (u^2 - (1+D) T) + eta_g^2 + I |v_i|^2] - 2 I common (v_i . u).
+    const double I = c->I;
+    const double k0 = common * (I * (m.ux * m.ux + m.uy * m.uy) - (1.0 + 2.0) * I * m.T);
+    const double px = -2.0 * I * common * m.ux, py = -2.0 * I * common * m.uy;
 #pragma unroll
-    for (int g2 = 0; g2 < 3; ++g2)
+    for (int g2 = 0; g2 < 3; ++g2) {
+        const double v = c->vg[g2];
+        const double ka = fma(common, c->eta2[g2] + I * (v * v), k0);          // |v_i|^2 = v^2
+        const double kd = fma(common, c->eta2[g2] + I * (2.0 * v * v), k0);    // |v_i|^2 = 2 v^2
+        const double qx = v * px, qy = v * py, sp = qx + qy, sm = qx - qy;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
-            const double cx = c->vg[g2] * DUX[d] - m.ux;
-            const double cy = c->vg[g2] * DUY[d] - m.uy;
-            const double br = base + c->I * (cx * cx + cy * cy) + c->eta2[g2];
-            src[8 * g2 + d] += feq[8 * g2 + d] * (common * br);
+            double br;
+            if (DUY[d] == 0) br = DUX[d] > 0 ? ka + qx : ka - qx;
+            else if (DUX[d] == 0) br = DUY[d] > 0 ? ka + qy : ka - qy;
+            else if (DUX[d] == DUY[d]) br = DUX[d] > 0 ? kd + sp : kd - sp;
+            else br = DUX[d] > 0 ? kd + sm : kd - sm;
+            src[8 * g2 + d] = fma(feq[8 * g2 + d], br, src[8 * g2 + d]);
         }
+    }
 }
 
 // Collision and chemistry of one cell.
