@@ -42,9 +42,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(tile=None):
     """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current kernel source and (when `tile` = (tile_x,
+    tile_y, lds) is given) on the same launch shape; else None."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
@@ -55,6 +56,11 @@ def measured_traffic():
                 vals[parts[0]] = parts[1]
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    if tile is not None:
+        import re
+        m = re.match(r"k_step(_lds)?<(\d+),(\d+),", vals.get("kernel", ""))
+        if not m or (int(m.group(2)), int(m.group(3)), 1 if m.group(1) else 0) != tuple(int(v) for v in tile):
+            return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -331,7 +337,7 @@ def main():
 
     achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
     ceiling = copy_ceiling_gbs()
-    traffic = measured_traffic()
+    traffic = measured_traffic(launch[:3])
     out = {
         "metric": "MLUPS (cell updates/s) FP64 at 2048\u00b2; batched & adjoint vs plain step time",
         "value": round(value, 2),
