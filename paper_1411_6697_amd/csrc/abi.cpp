@@ -481,16 +481,14 @@ lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
-    if (any_wall(ctx)) {   // wall sides run one shape (256 x 2, direct loads); nothing to tune
-        ctx->step_variant = 3;
-        if (choice) {
-            choice[0] = 256;
-            choice[1] = 2;
-            choice[2] = 0;
-            choice[3] = ctx->tile_order;
-        }
-        return LBKM_OK;
-    }
+    // wall sides run one shape (kWallTile, direct loads): only the tile order is tuned
+    int v_lo = 0, v_hi = kNumStepVariants;
+    if (any_wall(ctx))
+        for (int v = 0; v < kNumStepVariants; ++v)
+            if (kStepVariants[v][0] == kWallTile[0] && kStepVariants[v][1] == kWallTile[1] && kStepVariants[v][2] == 0) {
+                v_lo = v;
+                v_hi = v + 1;
+            }
     const int64_t cells = ctx->pitch * (int64_t)ctx->grid.ny;
     const int cur = ctx->cur;
     const int64_t steps0 = ctx->steps;
@@ -507,7 +505,7 @@ lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     int best_v = ctx->step_variant, best_o = ctx->tile_order;
     float best_ms = 1e30f;
     const int trial = 4;
-    for (int v = 0; v < kNumStepVariants && e == hipSuccess; ++v)
+    for (int v = v_lo; v < v_hi && e == hipSuccess; ++v)
         for (int o = 0; o < 2 && e == hipSuccess; ++o) {
             ctx->step_variant = v;
             ctx->tile_order = o;

@@ -9,6 +9,7 @@ namespace lbkm {
 
 extern const int kStepVariants[][3];   // {tile_x, tile_y, lds} per launch variant (step.hip)
 extern const int kNumStepVariants;
+extern const int kWallTile[2];          // {tile_x, tile_y} of the wall specialisation (direct loads)
 int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
 // vertical != 0: XCD-contiguous bands of tile columns (when the tile columns divide by
 // eight), else bands of tile rows

@@ -448,6 +448,7 @@ hipError_t launch_shape(const Consts* dc, int flags, int nx, int ny, const doubl
 // in LDS; lds = 0 reads the stencil straight from the caches.
 const int kStepVariants[][3] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}, {256, 2, 0}, {256, 1, 0}, {64, 4, 0}};
 const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
+const int kWallTile[2] = {64, 4};   // the one shape compiled with the wall (ghost-layer) stencil
 
 int step_flags(const Consts& c) {
     const bool chem = c.chem != 0;
@@ -460,11 +461,11 @@ hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
                        int vertical, hipStream_t st, const Blend* bl, const double* gb) {
     if (gb) {
-        // wall sides: the 256 x 2 direct shape, whatever the tuned one
-        if (bl) return launch_flags<256, 2, false, true, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout,
+        // wall sides: the 64 x 4 direct shape (kWallTile), whatever the tuned one
+        if (bl) return launch_flags<64, 4, false, true, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout,
                                                                vertical, st, *bl, gb);
         const Blend none{nullptr, nullptr, 0.0, 1.0};
-        return launch_flags<256, 2, false, false, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical,
+        return launch_flags<64, 4, false, false, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical,
                                                         st, none, gb);
     }
     switch (variant) {

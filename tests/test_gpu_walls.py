@@ -111,3 +111,19 @@ def test_walls_with_srt_collision_and_rk3():
     P, tab, f, lam = oracle_run(w, fields=F)
     assert P.tau > 0 and P.rk == 3
     _assert_parity(g, P, tab, f, lam, label="walls + SRT + RK3")
+
+
+def test_autotune_with_walls_keeps_the_wall_shape_and_results():
+    """With wall sides only the tile order is tuned; the tuned run equals an untuned one."""
+    from paper_1411_6697_amd import lbkm
+    w = W.shock_reflection(nx=67, ny=29, steps=20)
+    a = lbkm.sim_from_workload(w)
+    choice = a.autotune()
+    assert tuple(choice[:3]) == (64, 4, 0), choice
+    a.step(w.steps)
+    b = lbkm.sim_from_workload(w)
+    b.set_tile_order(1 - choice[3])
+    b.step(w.steps)
+    fa, la = a.get_state()
+    fb, lb = b.get_state()
+    assert torch.equal(fa, fb) and torch.equal(la, lb)
