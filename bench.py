@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--no-srt", action="store_true")
     ap.add_argument("--no-rk", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="fix the KH step's launch instead of autotuning it: TXxTY[l]:ORDER, e.g. 64x4:1 "
+                         "(l = LDS staging, ORDER 1 = column bands); used to profile a stated shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -279,7 +282,15 @@ def main():
     w = W.kh(n=args.n, steps=args.steps, reactive=True)
     cells = w.nx * w.ny
     sim = lbkm.sim_from_workload(w)
-    launch = sim.autotune()                     # launch shape: tile, LDS staging, tile order
+    if args.launch:
+        shape, order = args.launch.split(":")
+        lds = 1 if shape.endswith("l") else 0
+        tx, ty = (int(v) for v in shape.rstrip("l").split("x"))
+        sim.set_tile(tx, ty, lds)
+        sim.set_tile_order(int(order))
+        launch = (tx, ty, lds, int(order))
+    else:
+        launch = sim.autotune()                 # launch shape: tile, LDS staging, tile order
     ms = time_steps(sim, args.steps, args.warmup)
     ok = sim.check()
     del sim

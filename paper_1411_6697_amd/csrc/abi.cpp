@@ -504,7 +504,7 @@ lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     if (e == hipSuccess) e = hipEventCreate(&t1);
     int best_v = ctx->step_variant, best_o = ctx->tile_order;
     float best_ms = 1e30f;
-    const int trial = 4;
+    const int trial = 8;          // the closest shapes differ by about 1 %: long enough to rank them
     for (int v = v_lo; v < v_hi && e == hipSuccess; ++v)
         for (int o = 0; o < 2 && e == hipSuccess; ++o) {
             ctx->step_variant = v;
