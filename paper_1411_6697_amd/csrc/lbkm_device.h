@@ -429,6 +429,18 @@ __device__ __forceinline__ void load_cell(const Soa& f, uint32_t off, double v[N
     }
 }
 
+// load_cell issued at raised wave priority: the other waves of the SIMD, usually deep in
+// their collision arithmetic, do not hold up the start of this memory phase.  Used for the
+// centre values of the single-grid step (it made the 256-thread tiles at three waves per
+// SIMD the fastest launch); the persistent batch kernel runs slightly slower with it.
+__device__ __forceinline__ void load_cell_first(const Soa& f, uint32_t off, double v[NV]) {
+    __builtin_amdgcn_s_setprio(1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_cell(f, off, v);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
+}
+
 // neighbour index along one axis with the boundary rule (periodic wrap or clamp)
 __device__ __forceinline__ int wrap(int j, int n, int bc) {
     if (bc == 0) {   // periodic

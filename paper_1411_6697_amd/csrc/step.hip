@@ -117,7 +117,7 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
                                             const Ghosts* gh = nullptr) {
     double f[NV];
     if (SRT) {
-        load_cell(F, s.c, f);
+        load_cell_first(F, s.c, f);
         m = macro_sums(c, f);
         lam = ld(L, 0u, s.c);
         srt_source<CHEM, GEXP>(c, M, lam, m, f, src, dlam);
@@ -140,14 +140,7 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
         gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
         gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
     }
-    // The wave issues its 24 centre loads at raised priority, so that the other wave of the
-    // SIMD (usually deep in its collision arithmetic) does not hold up the start of a memory
-    // phase (about 1 % faster in the tile order the autotuner picks).
-    __builtin_amdgcn_s_setprio(1);
-    __builtin_amdgcn_sched_barrier(0);
-    load_cell(F, s.c, f);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_setprio(0);
+    load_cell_first(F, s.c, f);
     Blocks sb, h;
     to_combos(f, sb);
     forward(M, sb, h);
