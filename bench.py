@@ -13,6 +13,7 @@ SSP Runge-Kutta time schemes, and between reflecting walls.  Prints one JSON lin
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
                   [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk] [--no-walls]
+                  [--launch TXxTY[l]:ORDER]   (fix the step's launch instead of autotuning it)
 """
 
 from __future__ import annotations
