@@ -433,10 +433,14 @@ __device__ __forceinline__ void load_cell(const Soa& f, uint32_t off, double v[N
 // their collision arithmetic, do not hold up the start of this memory phase.  Used for the
 // centre values of the single-grid step (it made the 256-thread tiles at three waves per
 // SIMD the fastest launch); the persistent batch kernel runs slightly slower with it.
-__device__ __forceinline__ void load_cell_first(const Soa& f, uint32_t off, double v[NV]) {
+// With l given, the cell's lambda is loaded in the same window (its latency would otherwise
+// surface just before the reaction step).
+__device__ __forceinline__ void load_cell_first(const Soa& f, uint32_t off, double v[NV],
+                                                const Soa* l = nullptr, double* lam = nullptr) {
     __builtin_amdgcn_s_setprio(1);
     __builtin_amdgcn_sched_barrier(0);
     load_cell(f, off, v);
+    if (l) *lam = ld(*l, 0u, off);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_setprio(0);
 }

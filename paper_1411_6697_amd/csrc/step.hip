@@ -117,9 +117,8 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
                                             const Ghosts* gh = nullptr) {
     double f[NV];
     if (SRT) {
-        load_cell_first(F, s.c, f);
+        load_cell_first(F, s.c, f, &L, &lam);
         m = macro_sums(c, f);
-        lam = ld(L, 0u, s.c);
         srt_source<CHEM, GEXP>(c, M, lam, m, f, src, dlam);
         return;
     }
@@ -140,14 +139,13 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
         gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
         gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
     }
-    load_cell_first(F, s.c, f);
+    load_cell_first(F, s.c, f, &L, &lam);
     Blocks sb, h;
     to_combos(f, sb);
     forward(M, sb, h);
     m = macro_of(h, c->DI);
     double A8 = 0.0, A9 = 0.0;
     if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
-    lam = ld(L, 0u, s.c);
     local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
 }
 
