@@ -133,13 +133,22 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
         gxy = (sld<true>(Ui, 0u, s.yp1, *Gb, gx0, *gh, 6) - sld<true>(Ui, 0u, s.ym1, *Gb, gx0, *gh, 5)) * c->half_inv_dy;
         gyy = (sld<true>(Ui, up, s.yp1, *Gb, gy0, *gh, 6) - sld<true>(Ui, up, s.ym1, *Gb, gy0, *gh, 5)) * c->half_inv_dy;
     } else if (AMOD) {
+        // the four neighbours' velocities join the raised-priority window of the centre loads
         const uint32_t up = opaque(Ui.plane_bytes);
-        gxx = (ld(Ui, 0u, s.xp1) - ld(Ui, 0u, s.xm1)) * c->half_inv_dx;   // d u_x / dx
-        gyx = (ld(Ui, up, s.xp1) - ld(Ui, up, s.xm1)) * c->half_inv_dx;   // d u_y / dx
-        gxy = (ld(Ui, 0u, s.yp1) - ld(Ui, 0u, s.ym1)) * c->half_inv_dy;   // d u_x / dy
-        gyy = (ld(Ui, up, s.yp1) - ld(Ui, up, s.ym1)) * c->half_inv_dy;   // d u_y / dy
+        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_sched_barrier(0);
+        const double a0 = ld(Ui, 0u, s.xp1), a1 = ld(Ui, 0u, s.xm1), a2 = ld(Ui, up, s.xp1), a3 = ld(Ui, up, s.xm1);
+        const double b0 = ld(Ui, 0u, s.yp1), b1 = ld(Ui, 0u, s.ym1), b2 = ld(Ui, up, s.yp1), b3 = ld(Ui, up, s.ym1);
+        load_cell(F, s.c, f);
+        lam = ld(L, 0u, s.c);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
+        gxx = (a0 - a1) * c->half_inv_dx;   // d u_x / dx
+        gyx = (a2 - a3) * c->half_inv_dx;   // d u_y / dx
+        gxy = (b0 - b1) * c->half_inv_dy;   // d u_x / dy
+        gyy = (b2 - b3) * c->half_inv_dy;   // d u_y / dy
     }
-    load_cell_first(F, s.c, f, &L, &lam);
+    if constexpr (!AMOD || GHOST) load_cell_first(F, s.c, f, &L, &lam);
     Blocks sb, h;
     to_combos(f, sb);
     forward(M, sb, h);
