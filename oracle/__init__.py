@@ -42,12 +42,20 @@ the mathematics, never against the oracle itself):
                         half-range flux of the equilibria; the shock-reflection states
                         (physics.oblique_shock reproduces the paper's incident shock)
   modification_terms    its sign: only the chosen sign makes the viscous heating
-                        independent of R_8 (Chapman-Enskog, Sec. III)
+                        independent of R_8 (Chapman-Enskog, Sec. III), in a 1D wave and,
+                        with the 1/R_8 part extrapolated away, in a 2D shear flow where
+                        the shear term of A_hat_8 and every term of A_hat_9 are non-zero;
+                        the exchange of the x and y axes maps solutions to solutions
+                        (A_hat_9 is A_hat_8 mirrored, term by term); planted mistakes (a
+                        dropped shear term, an exchanged derivative, a wrong velocity
+                        factor) fail these
   cochran_increment     exact solution of the rate equation (against a fine RK4);
                         homogeneous heating 2 Q dlambda / (D + I)
-  chemical_term         moments k = 1..9 equal the printed C_hat (Sec. II); the
-                        energy budget on a periodic grid.  Moments k >= 10:
-                        parity unpinned (the paper prints no value for them)
+  chemical_term         moments k = 1..9 equal the printed C_hat (Sec. II); for each
+                        of the 24 velocities C_i / f^eq_i equals (2 Q F / (D+I)) times
+                        the temperature derivative of log Eq. feq_continuous at
+                        (v_i, eta_i) (Eqs. M_chemical_2, M_chemical_feq), which fixes the
+                        bracket for every moment; the energy budget on a periodic grid
   nnd_derivative,       exact on linear data, zero on constants, upwind, second
   streaming             order on smooth monotone data, mirror symmetry
   step, run, init_f     Sod (I = 3), Lax (I = 1) and Sjogren (I = 4) against the exact

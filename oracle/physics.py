@@ -14,6 +14,7 @@ paper compares its simulations with, computed from their own mathematics.
                    detonation (the ZND spike, Sec. IV A and Sec. VI).
 * maxwellian_moments : moments of the continuous equilibrium distribution
                    Eq. feq_continuous by tensor Gauss-Hermite quadrature.
+* maxwellian     : Eq. feq_continuous itself, evaluated pointwise.
 """
 
 from __future__ import annotations
@@ -190,3 +191,12 @@ def maxwellian_moments(rho, ux, uy, T, I, polys, npts: int = 12):
     VX, VY, ET = np.meshgrid(ux + sx * x, uy + sx * x, se * x, indexing="ij")
     W = w[:, None, None] * w[None, :, None] * w[None, None, :]
     return np.array([rho * np.sum(W * p) for p in polys(VX, VY, ET)])
+
+
+def maxwellian(rho, ux, uy, T, I, vx, vy, eta, D: int = 2):
+    """The continuous equilibrium distribution of Eq. feq_continuous evaluated at the
+    velocity (vx, vy) and internal-degree variable eta:
+    rho (2 pi T)^(-D/2) (2 pi I T)^(-1/2) exp(-|v - u|^2 / (2 T) - eta^2 / (2 I T))."""
+    c2 = (vx - ux) ** 2 + (vy - uy) ** 2
+    return rho * (2.0 * math.pi * T) ** (-0.5 * D) * (2.0 * math.pi * I * T) ** -0.5 * \
+        np.exp(-c2 / (2.0 * T) - eta * eta / (2.0 * I * T))

@@ -378,6 +378,162 @@ def test_modification_sign_makes_viscous_heating_independent_of_R8():
     assert abs(wrong[k] - ce[k]) > 0.5 * abs(ce[k])
 
 
+def _swap_index(vx, vy):
+    """Index j(i) of the velocity (v_y, v_x) of velocity i: the velocity set with its axes
+    exchanged (each group maps to itself)."""
+    return [next(j for j in range(24) if vx[j] == vy[i] and vy[j] == vx[i]) for i in range(24)]
+
+
+# R_1..R_24 that the exchange of axes maps to themselves (moment pairs 5/7, 8/9, 10/13,
+# 11/12, 14/16, 17/19, 21/22, 23/24), with A_hat active: R_8 = R_9 != R_5 = R_7
+_SWAP_R = W.rates(1.2e4, r5=1e4, r7=1e4, r8=2.5e4, r9=2.5e4, r10=1.4e4, r13=1.4e4, r11=1.7e4, r12=1.7e4,
+                  r14=3e4, r16=3e4, r17=2e4, r19=2e4, r21=4e4, r22=4e4, r23=4.5e4, r24=4.5e4)
+
+
+def _wrong_a9_axis(rho, ux, uy, T, P, tab, upad=None):
+    """Planted mistake: A_hat_9's normal-strain factor takes d u_x/dx where d u_y/dy belongs."""
+    A8, A9 = _real_modification(rho, ux, uy, T, P, tab, upad)
+    nx, ny = rho.shape[1], rho.shape[0]
+    gx = om.ghost(ux, 1, P.bc_x, 1)
+    gy = om.ghost(uy, 0, P.bc_y, 1)
+    dux_dx = (gx[:, 2:nx + 2] - gx[:, 0:nx]) / (2.0 * P.dx)
+    duy_dy = (gy[2:ny + 2, :] - gy[0:ny, :]) / (2.0 * P.dy)
+    R7, R9 = tab.R[6], tab.R[8]
+    return A8, A9 + rho * T * (R7 - R9) / R7 * 4.0 * uy * (dux_dx - duy_dy)
+
+
+def _wrong_a9_cross(rho, ux, uy, T, P, tab, upad=None):
+    """Planted mistake: A_hat_9's shear term weighted by u_y instead of u_x."""
+    A8, A9 = _real_modification(rho, ux, uy, T, P, tab, upad)
+    A8y, _ = _real_modification(rho, uy, ux, T, P, tab, upad)      # not used: keeps the call shape
+    nx, ny = rho.shape[1], rho.shape[0]
+    gx = om.ghost(uy, 1, P.bc_x, 1)
+    gy = om.ghost(ux, 0, P.bc_y, 1)
+    shear = (gx[:, 2:nx + 2] - gx[:, 0:nx]) / (2.0 * P.dx) + (gy[2:ny + 2, :] - gy[0:ny, :]) / (2.0 * P.dy)
+    R7, R9 = tab.R[6], tab.R[8]
+    return A8, A9 + rho * T * (R7 - R9) / R7 * 2.0 * (uy - ux) * shear
+
+
+_real_modification = om.modification_terms
+
+
+def _transposition_mismatch(planted=None, steps=12):
+    """Run a random smooth 2D state and its transpose (axes exchanged, u_x <-> u_y, boundary
+    rules exchanged) and return the largest relative difference between the transposed
+    solution and the solution of the transposed problem."""
+    nx, ny = 11, 8
+    g = np.random.default_rng(21)
+    X, Y = np.meshgrid((np.arange(nx) + 0.5) / nx, (np.arange(ny) + 0.5) / ny)
+    ph = g.uniform(0, 2 * np.pi, 8)
+    F = dict(rho=1.0 + 0.2 * np.sin(2 * np.pi * X + ph[0]) * np.cos(2 * np.pi * Y + ph[1]),
+             ux=0.3 * np.cos(2 * np.pi * (X + 2 * Y) + ph[2]), uy=0.25 * np.sin(2 * np.pi * (2 * X - Y) + ph[3]),
+             T=1.3 + 0.3 * np.cos(2 * np.pi * X + ph[4]) * np.sin(2 * np.pi * Y + ph[5]),
+             lam=0.5 + 0.4 * np.sin(2 * np.pi * (X + Y) + ph[6]))
+    base = dict(R=_SWAP_R, dx=1e-3, dy=1e-3, dt=1e-5, Q=1.0, omega1=2.0, omega2=100.0)
+    runs = []
+    for transposed in (False, True):
+        if transposed:
+            t = {k: torch.from_numpy(np.ascontiguousarray(v.T)) for k, v in F.items()}
+            t["ux"], t["uy"] = t["uy"], t["ux"]
+            P = _params(bc_x="periodic", bc_y="outflow", **base)
+        else:
+            t = {k: torch.from_numpy(v) for k, v in F.items()}
+            P = _params(bc_x="outflow", bc_y="periodic", **base)
+        tab = om.make_tables(P)
+        f = om.init_f(t["rho"], t["ux"], t["uy"], t["T"], P, tab)
+        if planted is not None:
+            om.modification_terms = planted
+        try:
+            f, lam = om.run(f, t["lam"], P, tab, steps)
+        finally:
+            om.modification_terms = _real_modification
+        runs.append((f, lam, tab))
+    (f, lam, tab), (fT, lamT, _) = runs
+    sw = _swap_index(tab.vx.numpy(), tab.vy.numpy())
+    back = fT[sw].transpose(1, 2)                     # f_i(y, x) of the original problem
+    err_f = float(((back - f).abs() / f.abs().max()).max())
+    err_l = float((lamT.T - lam).abs().max())
+    return max(err_f, err_l)
+
+
+def test_exchanging_the_axes_maps_solutions_to_solutions():
+    """D2V24 maps to itself when the x and y axes are exchanged (Sec. II): velocity (v_x, v_y)
+    goes to (v_y, v_x) within the same group, and moments 5/7, 8/9, 10/13, 11/12, 14/16, 17/19,
+    21/22, 23/24 trade places.  With dx = dy and rates that respect that pairing (here
+    R_8 = R_9 != R_5 = R_7, so A_hat is active) the step commutes with the exchange: a random
+    2D state with u_x, u_y != 0 and its transpose give transposed solutions (12 steps, the
+    reaction running, outflow in one axis and periodic in the other).  This ties A_hat_9
+    (Eq. ArtificialA9) to A_hat_8 (Eq. ArtificialA8) term by term; an exchanged derivative in
+    A_hat_9, or its shear term weighted by the wrong velocity component (planted on the
+    oracle), breaks the symmetry."""
+    assert _transposition_mismatch() < 1e-12
+    assert _transposition_mismatch(_wrong_a9_axis) > 1e-6
+    assert _transposition_mismatch(_wrong_a9_cross) > 1e-6
+
+
+def _drop_a8_shear(rho, ux, uy, T, P, tab, upad=None):
+    """Planted mistake: A_hat_8 without its shear term 2 u_y (d_x u_y + d_y u_x)."""
+    A8, A9 = _real_modification(rho, ux, uy, T, P, tab, upad)
+    nx, ny = rho.shape[1], rho.shape[0]
+    gx = om.ghost(uy, 1, P.bc_x, 1)
+    gy = om.ghost(ux, 0, P.bc_y, 1)
+    shear = (gx[:, 2:nx + 2] - gx[:, 0:nx]) / (2.0 * P.dx) + (gy[2:ny + 2, :] - gy[0:ny, :]) / (2.0 * P.dy)
+    R5, R8 = tab.R[4], tab.R[7]
+    return A8 - rho * T * (R5 - R8) / R5 * 2.0 * uy * shear, A9
+
+
+def _heat_flux_nonequilibrium_2d(R8, planted=None):
+    """Delta_8, Delta_9 after six relaxation times (R_5 = R_7 = 1e4) of a plane wave with wave
+    vector (1, 1) on a periodic 32 x 32 grid, velocity amplitude (0.06, 0.1) (neither along
+    nor across the wave, so u_y and the shear d_x u_y + d_y u_x do not vanish), uniform rho
+    and T at the start.  Returns the two Delta's and the Chapman-Enskog viscous-heating parts
+    -rho T B_8 / R_5 and -rho T B_9 / R_7 of f_hat_8^(1), f_hat_9^(1) (Sec. III)."""
+    n = 32
+    R = W.rates(1e5, r5=1e4, r6=1e4, r7=1e4, r8=R8, r9=R8)
+    P = _params(R=R, dx=1.0 / n, dy=1.0 / n, dt=1e-6, bc_x="periodic", bc_y="periodic")
+    tab = om.make_tables(P)
+    X, Y = np.meshgrid((np.arange(n) + 0.5) / n, (np.arange(n) + 0.5) / n)
+    s = np.sin(2 * np.pi * (X + Y))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    one = np.ones((n, n))
+    f = om.init_f(t(one), t(0.06 * s), t(0.1 * s), t(one), P, tab)
+    if planted is not None:
+        om.modification_terms = planted
+    try:
+        f, lam = om.run(f, t(0 * one), P, tab, 600)
+    finally:
+        om.modification_terms = _real_modification
+    fhat = om.moment_transform(f, tab)
+    rho, ux, uy, T = om.macroscopic(fhat, P.I)
+    feq = om.equilibrium_moments(rho, ux, uy, T, P.I)
+    d8, d9 = (fhat[7] - feq[7]).numpy(), (fhat[8] - feq[8]).numpy()
+    ux, uy, rT = ux.numpy(), uy.numpy(), (rho * T).numpy()
+    cd = lambda a, ax: (np.roll(a, -1, ax) - np.roll(a, 1, ax)) * n / 2
+    uxx, uxy, uyx, uyy = cd(ux, 1), cd(ux, 0), cd(uy, 1), cd(uy, 0)
+    div = (uxx + uyy) / (2 + P.I)
+    B8 = 4 * ux * (uxx - div) + 2 * uy * (uyx + uxy)
+    B9 = 4 * uy * (uyy - div) + 2 * ux * (uyx + uxy)
+    return d8, d9, -rT * B8 / R[4], -rT * B9 / R[6]
+
+
+def test_modification_makes_viscous_heating_independent_of_R8_in_2d_shear():
+    """The 2D form of the viscous-heating pin (Sec. III, Eqs. NSEnergy_old/NSEnergy_new).  To
+    first order f_hat_8^(1) = -rho T B_8 / R_5 + Y_8 / R_8 with B_8 = 4 u_x (d_x u_x - div u /
+    (D+I)) + 2 u_y (d_x u_y + d_y u_x): the viscous heating scales with 1/R_5 only because of
+    A_hat_8, and everything else that relaxes through moment 8 (the heat conduction, the
+    truncation error of the streaming) with 1/R_8.  Two runs with R_8 = R_5 and R_8 = 2 R_5
+    give V_8 = 2 Delta_8(2 R_5) - Delta_8(R_5), from which the 1/R_8 part has cancelled;
+    V_8 (and likewise V_9 with B_9) must equal -rho T B_8 / R_5 everywhere.  The shear term
+    carries about half of B_8 in this flow: A_hat_8 without it (planted on the oracle)
+    misses by more than half."""
+    a8, a9, ce8, ce9 = _heat_flux_nonequilibrium_2d(1e4)
+    b8, b9, _, _ = _heat_flux_nonequilibrium_2d(2e4)
+    for V, ce in ((2 * b8 - a8, ce8), (2 * b9 - a9, ce9)):
+        assert np.max(np.abs(V - ce)) < 0.05 * np.max(np.abs(ce))
+    w8, _, _, _ = _heat_flux_nonequilibrium_2d(2e4, planted=_drop_a8_shear)
+    assert np.max(np.abs(2 * w8 - a8 - ce8)) > 0.5 * np.max(np.abs(ce8))
+
+
 # ---------------------------------------------------------------------------
 # Chemistry (Sec. II, assumptions 3-5, Eqs. M_chemical_T, C_i, lambda_equation)
 # ---------------------------------------------------------------------------
@@ -399,6 +555,46 @@ def test_chemical_term_moments_match_printed_C_hat():
         want = [0, 0, 0, q, q / (2 + I), 0, q / (2 + I), q * ux * (4 + I) / (2 + I),
                 q * uy * (4 + I) / (2 + I)]
         assert np.allclose(Ch, want, rtol=1e-10, atol=1e-11 * q)
+
+
+def _chemical_term_wrong_eta(feq, ux, uy, T, F, P, tab):
+    """Planted mistake: each group takes the next group's eta."""
+    import dataclasses
+    return om.chemical_term(feq, ux, uy, T, F, P, dataclasses.replace(tab, eta=tab.eta.roll(8)))
+
+
+def _chemical_term_no_drift(feq, ux, uy, T, F, P, tab):
+    """Planted mistake: |v_i|^2 where |v_i - u|^2 belongs."""
+    return om.chemical_term(feq, 0 * ux, 0 * uy, T, F, P, tab)
+
+
+@pytest.mark.parametrize("d,I", [(W.DVM_UNSTEADY_DET, 3.0), (W.DVM_STEADY_DET, 3.0),
+                                 ((0.8, 1.2, 1.3, 1.0, 2.7, 0.8), 2.0), (W.DVM_SJOGREN, 4.0)])
+def test_chemical_term_is_the_temperature_derivative_of_the_maxwellian(d, I):
+    """Eqs. M_chemical_2, M_chemical_feq, M_chemical_T: C_i / f^eq_i equals
+    (2 Q F / (D+I)) d ln f^eq / dT of the continuous Maxwellian (Eq. feq_continuous) at the
+    discrete velocity v_i and internal variable eta_i, for each of the 24 velocities (this
+    pins the bracket of Eq. C_i for every moment, k >= 10 included).  The derivative is a
+    central difference in T of physics.maxwellian.  A group that takes another group's
+    eta, or |v_i|^2 in place of |v_i - u|^2 (both planted on the oracle), fails."""
+    P = _params(dvm=d, I=I, Q=1.7)
+    tab = om.make_tables(P)
+    t = lambda v: torch.full((1, 1), v, dtype=T64)
+    rho, ux, uy, T, F = 1.3, 0.35, -0.2, 1.6, 0.8
+    feq = torch.einsum("ik,k...->i...", tab.Minv, om.equilibrium_moments(t(rho), t(ux), t(uy), t(T), I))
+    vx, vy, eta = tab.vx.numpy(), tab.vy.numpy(), tab.eta.numpy()
+    h = 1e-5 * T
+    dlog = (np.log(physics.maxwellian(rho, ux, uy, T + h, I, vx, vy, eta))
+            - np.log(physics.maxwellian(rho, ux, uy, T - h, I, vx, vy, eta))) / (2 * h)
+    want = 2.0 * P.Q * F / (2.0 + I) * dlog
+    scale = np.abs(want).max()
+
+    def ratio(fun):
+        return (fun(feq, t(ux), t(uy), t(T), t(F), P, tab)[:, 0, 0] / feq[:, 0, 0]).numpy()
+
+    assert np.max(np.abs(ratio(om.chemical_term) - want)) < 1e-8 * scale
+    assert np.max(np.abs(ratio(_chemical_term_wrong_eta) - want)) > 1e-3 * scale
+    assert np.max(np.abs(ratio(_chemical_term_no_drift) - want)) > 1e-3 * scale
 
 
 def _rk4(fun, y, t1, n=4000):
