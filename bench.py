@@ -13,7 +13,7 @@ SSP Runge-Kutta time schemes, and between reflecting walls.  Prints one JSON lin
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
                   [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk] [--no-walls]
-                  [--launch TXxTY[l]:ORDER]   (fix the step's launch instead of autotuning it)
+                  [--launch TXxTY[l|s]:ORDER]   (fix the step's launch instead of autotuning it)
 """
 
 from __future__ import annotations
@@ -59,8 +59,9 @@ def measured_traffic(tile=None):
         return None
     if tile is not None:
         import re
-        m = re.match(r"k_step(_lds)?<(\d+),(\d+),", vals.get("kernel", ""))
-        if not m or (int(m.group(2)), int(m.group(3)), 1 if m.group(1) else 0) != tuple(int(v) for v in tile):
+        m = re.match(r"k_step(_lds|_sf)?<(\d+),(\d+),", vals.get("kernel", ""))
+        mode = {None: 0, "_lds": 1, "_sf": 2}[m.group(1)] if m else -1
+        if not m or (int(m.group(2)), int(m.group(3)), mode) != tuple(int(v) for v in tile):
             return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -267,8 +268,9 @@ def main():
     ap.add_argument("--no-rk", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--launch", default=None,
-                    help="fix the KH step's launch instead of autotuning it: TXxTY[l]:ORDER, e.g. 64x4:1 "
-                         "(l = LDS staging, ORDER 1 = column bands); used to profile a stated shape")
+                    help="fix the KH step's launch instead of autotuning it: TXxTY[l|s]:ORDER, e.g. 64x4s:1 "
+                         "(l = LDS-staged stencil, s = stream-first kernel, ORDER 1 = column bands); used to "
+                         "profile a stated shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -285,8 +287,8 @@ def main():
     sim = lbkm.sim_from_workload(w)
     if args.launch:
         shape, order = args.launch.split(":")
-        lds = 1 if shape.endswith("l") else 0
-        tx, ty = (int(v) for v in shape.rstrip("l").split("x"))
+        lds = 1 if shape.endswith("l") else (2 if shape.endswith("s") else 0)
+        tx, ty = (int(v) for v in shape.rstrip("ls").split("x"))
         sim.set_tile(tx, ty, lds)
         sim.set_tile_order(int(order))
         launch = (tx, ty, lds, int(order))

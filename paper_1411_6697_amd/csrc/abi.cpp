@@ -421,7 +421,7 @@ lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam) {
 lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t lds) {
     if (!ctx) return LBKM_EINVAL;
     for (int v = 0; v < kNumStepVariants; ++v)
-        if (kStepVariants[v][0] == tile_x && kStepVariants[v][1] == tile_y && kStepVariants[v][2] == (lds ? 1 : 0)) {
+        if (kStepVariants[v][0] == tile_x && kStepVariants[v][1] == tile_y && kStepVariants[v][2] == lds) {
             ctx->step_variant = v;
             return LBKM_OK;
         }

@@ -132,9 +132,10 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
         for (int d = 0; d < 8; ++d) {
             const uint32_t so = (uint32_t)(8 * g + d) * pb;
             const double f0 = ld(F, so, oc);
-            double out = fma(dt, src[8 * g + d], f0);
-            if (DUX[d] > 0) out = fma(-wx, nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)), out);
-            if (DUX[d] < 0) out = fma(wx, nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)), out);
+            double a = f0;
+            if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)), a);
+            if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)), a);
+            double out = fma(dt, src[8 * g + d], a);
             if (AMOD) vel_add(va, c, g, d, out);
             st(G, so, oc, out);
         }

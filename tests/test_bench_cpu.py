@@ -23,8 +23,8 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def _profiled_tile():
     with open(bench.PMC_FILE) as fh:
         text = fh.read()
-    m = re.search(r"^kernel k_step(_lds)?<(\d+),(\d+),", text, re.M)
-    return int(m.group(2)), int(m.group(3)), 1 if m.group(1) else 0
+    m = re.search(r"^kernel k_step(_lds|_sf)?<(\d+),(\d+),", text, re.M)
+    return int(m.group(2)), int(m.group(3)), {None: 0, "_lds": 1, "_sf": 2}[m.group(1)]
 
 
 def test_committed_traffic_is_read_only_for_its_own_source_and_launch():
