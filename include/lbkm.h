@@ -252,6 +252,17 @@ lbkm_status lbkm_adjoint_init(lbkm_ctx* ctx, const double* rho, const double* ux
  * NULL).  Asynchronous. */
 lbkm_status lbkm_tne_loss(lbkm_ctx* ctx, const double* f, double* loss_dev, double* grad_f);
 
+/* lbkm_tne_loss for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): the same kernels and the same result, bitwise, but the
+ * per-work-group partial sums live in a fixed library array in device memory (512 KiB per
+ * GPU, held until the process ends) instead of the context's lazily allocated adjoint
+ * scratch, and the call makes no hipMalloc/hipFree or other allocating call.  Arguments,
+ * layout and ownership as lbkm_tne_loss; asynchronous on the context's stream.  Errors: as
+ * lbkm_tne_loss, plus LBKM_EINVAL when ceil(nx/256) * ny > 65536 (more partial sums than
+ * the array holds).  Every call on one GPU shares that array: calls that overlap in time on
+ * one GPU (other streams, other threads) race and must be ordered by the caller. */
+lbkm_status lbkm_tne_loss_noalloc(lbkm_ctx* ctx, const double* f, double* loss_dev, double* grad_f);
+
 /* Plain streaming copy of n doubles src -> dst (device pointers, 16-byte aligned) on
  * hip_stream; a bandwidth reference for the step kernel's roofline (asynchronous). */
 lbkm_status lbkm_copy_kernel(const double* src, double* dst, int64_t n, void* hip_stream);

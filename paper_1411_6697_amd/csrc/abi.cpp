@@ -127,6 +127,7 @@ lbkm_status ensure_device_tables(lbkm_ctx* ctx) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->partials, sizeof(double) * 8 * kReduceBlocks);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->out8, sizeof(double) * 8);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->flag, sizeof(int));
+    if (e == hipSuccess) e = setup_noalloc_scratch();   // lbkm_tne_loss_noalloc's scratch on this device
     if (e != hipSuccess) return hip_fail(ctx, e, "allocation of library tables");
     return LBKM_OK;
 }

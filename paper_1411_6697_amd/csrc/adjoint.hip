@@ -19,6 +19,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lbkm_abi_internal.h"
 #include "lbkm_device.h"
 #include "lbkm_kernels.h"
@@ -780,17 +782,58 @@ lbkm_status ensure_adjoint_scratch(lbkm_ctx* ctx) {
     return LBKM_OK;
 }
 
-lbkm_status adj_ready(lbkm_ctx* ctx) {
+// the checks of every adjoint entry point (no allocation)
+lbkm_status adj_check(lbkm_ctx* ctx) {
     if (!ctx) return LBKM_EINVAL;
     if ((int64_t)NV * ctx->grid.nx * ctx->grid.ny * 8 > 0xFFFFFFFFll)
         return fail(ctx, LBKM_EINVAL, "the adjoint needs a dense state below 4 GiB");
     if (ctx->batched) return fail(ctx, LBKM_ESTATE, "not available on a batched context");
     if (!ctx->bound) return fail(ctx, LBKM_ESTATE, "buffers not bound");
     if (!ctx->params) return fail(ctx, LBKM_ESTATE, "parameters not set");
-    return ensure_adjoint_scratch(ctx);
+    return LBKM_OK;
+}
+
+lbkm_status adj_ready(lbkm_ctx* ctx) {
+    const lbkm_status st = adj_check(ctx);
+    return st != LBKM_OK ? st : ensure_adjoint_scratch(ctx);
+}
+
+// Scratch of the allocation-free loss (lbkm_tne_loss_noalloc): the per-work-group partial
+// sums live in this file-scope device array, one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it only stands
+// for the symbol): it looks up each device's address once, with that device current, and
+// passes that address.
+constexpr int64_t kNoAllocPartials = 65536;          // 512 KiB
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+std::once_flag g_scratch_once[kMaxDevices];
+
+// address of `scratch` on the current device (looked up on the first call per device)
+hipError_t scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = static_cast<double*>(p);
+    });
+    if (g_scratch_err[dev] != hipSuccess) return g_scratch_err[dev];
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace
+
+// Looks up the allocation-free loss's scratch address on the current device (called when a
+// context's device tables are set up, so that the lookup happens outside any stream capture).
+hipError_t setup_noalloc_scratch() {
+    double* p = nullptr;
+    return scratch_address(&p);
+}
 
 }  // namespace lbkm
 
@@ -851,6 +894,26 @@ lbkm_status lbkm_tne_loss(lbkm_ctx* ctx, const double* f, double* loss_dev, doub
     hipLaunchKernelGGL(k_tne_loss, g, dim3(kAdjThreads), 0, ctx->stream, ctx->d, f, grad_f, part);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kAdjThreads), 0, ctx->stream, part, (int64_t)g.x * g.y, loss_dev);
     hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "loss kernels");
+}
+
+lbkm_status lbkm_tne_loss_noalloc(lbkm_ctx* ctx, const double* f, double* loss_dev, double* grad_f) {
+    lbkm_status st = adj_check(ctx);
+    if (st != LBKM_OK) return st;
+    if (!f || !loss_dev) return fail(ctx, LBKM_EINVAL, "NULL argument");
+    const int nx = ctx->grid.nx, ny = ctx->grid.ny;
+    const dim3 g = adj_grid(nx, ny);
+    const int64_t nb = (int64_t)g.x * g.y;
+    if (nb > kNoAllocPartials)
+        return fail(ctx, LBKM_EINVAL,
+                    "grid too large for the allocation-free loss: it needs ceil(nx/256) * ny partial sums, "
+                    "at most 65536");
+    double* part = nullptr;
+    hipError_t e = scratch_address(&part);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scratch address of the allocation-free loss");
+    hipLaunchKernelGGL(k_tne_loss, g, dim3(kAdjThreads), 0, ctx->stream, ctx->d, f, grad_f, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kAdjThreads), 0, ctx->stream, part, nb, loss_dev);
+    e = hipGetLastError();
     return e == hipSuccess ? LBKM_OK : hip_fail(ctx, e, "loss kernels");
 }
 

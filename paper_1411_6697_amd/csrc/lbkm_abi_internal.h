@@ -58,4 +58,5 @@ lbkm_status build_tables(lbkm_ctx* ctx, const lbkm_grid* g);
 lbkm_status upload_consts(lbkm_ctx* ctx);
 lbkm_status ensure_device_tables(lbkm_ctx* ctx);
 void destroy_extras(lbkm_ctx* ctx);
+hipError_t setup_noalloc_scratch();   // adjoint.hip: scratch address of lbkm_tne_loss_noalloc
 }  // namespace lbkm

@@ -73,6 +73,7 @@ SIGNATURES = {
     "lbkm_adjoint_step": [_P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_adjoint_init": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "lbkm_tne_loss": [_P, _P, _P, _P],
+    "lbkm_tne_loss_noalloc": [_P, _P, _P, _P],
     "lbkm_destroy": [_P],
     "lbkm_copy_kernel": [_P, _P, ctypes.c_int64, _P],
     "lbkm_batch_create": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Grid), _P,
@@ -303,6 +304,12 @@ class Sim:
         g = torch.empty_like(f) if grad else None
         self._call("lbkm_tne_loss", _ptr(f), _ptr(loss), _ptr(g))
         return loss[0], g
+
+    def tne_loss_into(self, f, loss, grad=None):
+        """The same loss into caller buffers through lbkm_tne_loss_noalloc (no device
+        allocation by the library or by this call): loss is a 1-element float64 device
+        tensor, grad None or a tensor shaped like f."""
+        self._call("lbkm_tne_loss_noalloc", _ptr(f), _ptr(loss), _ptr(grad))
 
 
 NUM_GRAD = 27   # R_1..R_24, Q, omega_1, omega_2
