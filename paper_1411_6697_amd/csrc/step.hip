@@ -493,119 +493,6 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
     st_stream(Lo, 0u, s.c, lnew);
 }
 
-// Resident-tile step (tiles one wave wide: a wave is one tile row of 64 cells).  Phase 1 is
-// the collision of k_step; the cell's 24 values also go to an LDS copy of the tile, padded
-// with two halo columns per side (loaded once per work-group), so that after one barrier
-// the NND stencil of phase 2 reads the centre value, the x neighbours and the y neighbours
-// inside the tile from LDS, and only the y neighbours in the rows above and below the tile
-// from the caches.  Every LDS slot holds the value the boundary rule assigns to its grid
-// position (wrapped or clamped), so ragged tiles and grids narrower than a tile need no
-// special case; threads past the grid's edge load, collide and stage the value of their
-// wrapped position but store nothing.
-template <int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
-__global__ __launch_bounds__(64 * TY, GEXP ? 2 : 3) void k_step_res(const Consts* __restrict__ c,
-                                                                 const double* __restrict__ fin,
-                                                                 double* __restrict__ fout,
-                                                                 const double* __restrict__ lin,
-                                                                 double* __restrict__ lout,
-                                                                 const double* __restrict__ uin,
-                                                                 double* __restrict__ uout, int gx, int ntiles,
-                                                                 int vertical, Blend bl) {
-    constexpr int TX = 64, NT = TX * TY, PW = TX + 4, PLANE = TY * PW;
-    constexpr int NH = 4 * TY * NV;                 // halo values of the tile (4 columns per row)
-    __shared__ double tile[NV * PLANE];             // [plane][row][x - x0 + 2]
-    int tx, ty;
-    if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;    // uniform over the work-group
-    const int tid = (int)threadIdx.x;
-    const int lx = tid % TX;
-    const int ly = __builtin_amdgcn_readfirstlane(tid / TX);             // one wave = one tile row
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int nx = c->nx, ny = c->ny;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool inside = x < nx && y < ny;
-    const int xw = wrap(x, nx, c->bc_x), yw = wrap(y, ny, c->bc_y);
-    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
-    const Soa L = soa(lin, 0), Lo = soa(lout, 0);
-    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
-    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
-    const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
-    // stencil offsets of the wrapped position (equal to the cell's own inside the grid)
-    const Off s = stencil_offsets(c, xw, yw);
-
-    // halo columns x0-2, x0-1, x0+64, x0+65 of every tile row and plane, spread over the threads
-    constexpr int HPT = (NH + NT - 1) / NT;
-    double hv[HPT];
-    int hslot[HPT];
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const int h = tid + j * NT;
-        hslot[j] = -1;
-        hv[j] = 0.0;
-        if (NH % NT == 0 || h < NH) {
-            const int p = h / (4 * TY), r = (h % (4 * TY)) / 4, k = h % 4;
-            const int col = k < 2 ? k : TX + k;                                   // 0, 1, 66, 67
-            const int gxp = wrap(x0 - 2 + col, nx, c->bc_x), gyp = wrap(y0 + r, ny, c->bc_y);
-            hslot[j] = p * PLANE + r * PW + col;
-            hv[j] = ld(F, (uint32_t)p * F.plane_bytes, ((uint32_t)gyp * (uint32_t)c->pitch + (uint32_t)gxp) * 8u);
-        }
-    }
-
-    // Phase 1: collision and chemistry from the 24 centre values, which are also staged
-    double src[NV], dlam, lam;
-    Macro m;
-    {
-        double f[NV];
-        load_cell_first(F, s.c, f);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) tile[i * PLANE + ly * PW + lx + 2] = f[i];
-#pragma unroll
-        for (int j = 0; j < HPT; ++j)
-            if (hslot[j] >= 0) tile[hslot[j]] = hv[j];
-        cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, L, Ui, s, src, dlam, lam, m);
-    }
-    __syncthreads();
-
-    // Phase 2: NND streaming from the staged tile; the rows beyond the tile from the caches
-    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
-    const uint32_t pb = opaque(F.plane_bytes);
-    VelAcc va;                                      // velocity of the new state (for A_hat)
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double v = c->vg[g];
-        const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int p = 8 * g + d;
-            const uint32_t so = (uint32_t)p * pb;
-            const double* q = tile + p * PLANE + ly * PW + lx + 2;
-            // y neighbour at row offset k: LDS inside the tile, else the state (wave-uniform)
-            auto yv = [&](int k, uint32_t off) { return (ly + k >= 0 && ly + k < TY) ? q[k * PW] : ld(F, so, off); };
-            const double f0 = q[0];
-            double a = f0;
-            if (DUX[d] > 0) a = fma(-wx, nnd_pos(q[-2], q[-1], f0, q[1]), a);
-            if (DUX[d] < 0) a = fma(wx, nnd_neg(q[-1], f0, q[1], q[2]), a);
-            if (DUY[d] > 0) a = fma(-wy, nnd_pos(yv(-2, s.ym2), yv(-1, s.ym1), f0, yv(1, s.yp1)), a);
-            if (DUY[d] < 0) a = fma(wy, nnd_neg(yv(-1, s.ym1), f0, yv(1, s.yp1), yv(2, s.yp2)), a);
-            double out = fma(dt, src[p], a);
-            if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
-            if (AMOD) vel_add(va, c, g, d, out);
-            if (inside) st_stream(G, so, s.c, out);
-        }
-    }
-    if (!inside) return;
-    if (AMOD) {
-        st_stream(Uo, 0u, s.c, va.jx / va.r);
-        st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
-    }
-    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
-                                    : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
-    const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
-                                    : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
-    double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
-    if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
-    st_stream(Lo, 0u, s.c, lnew);
-}
-
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
 // general, or walls meet A_hat and the reaction: the other specialisations then fit without
 // spilling, the compiler stops parking scalar registers in vector lanes, and the wall
@@ -650,11 +537,6 @@ hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, dou
     else if constexpr (MODE == 2)
         hipLaunchKernelGGL((k_step_sf<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
-    else if constexpr (MODE == 3) {
-        static_assert(MODE != 3 || TX == 64, "resident tiles are one wave wide");
-        hipLaunchKernelGGL((k_step_res<TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
-                           st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
-    }
     else
         hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND, GHOST>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl, gb);
@@ -693,11 +575,9 @@ hipError_t launch_shape(const Consts* dc, int flags, int nx, int ny, const doubl
 
 // Launch variants compiled in: {tile_x, tile_y, mode}.  mode 0 collides first and reads the
 // stencil straight from the caches; mode 1 collides first and stages each stencil plane in
-// LDS; mode 2 streams first (k_step_sf, each input value read from HBM once); mode 3 keeps
-// the tile resident in LDS between the two phases (k_step_res, 64-wide tiles only).
+// LDS; mode 2 streams first (k_step_sf, each input value read from HBM once).
 const int kStepVariants[][3] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}, {256, 2, 0}, {256, 1, 0}, {64, 4, 0},
-                                {64, 4, 2}, {32, 8, 2}, {128, 2, 2}, {256, 1, 2}, {64, 4, 3}, {64, 3, 3},
-                                {64, 2, 3}};
+                                {64, 4, 2}, {32, 8, 2}, {128, 2, 2}, {256, 1, 2}};
 const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 const int kWallTile[2] = {64, 4};   // the one shape compiled with the wall (ghost-layer) stencil
 
@@ -733,9 +613,6 @@ hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny,
         case 7: return launch_shape<32, 8, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         case 8: return launch_shape<128, 2, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         case 9: return launch_shape<256, 1, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
-        case 10: return launch_shape<64, 4, 3>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
-        case 11: return launch_shape<64, 3, 3>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
-        case 12: return launch_shape<64, 2, 3>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         default: return launch_shape<64, 4, 1>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
     }
 }

@@ -290,7 +290,7 @@ def test_ragged_and_degenerate_grids(nx, ny, bcx, bcy):
 
 
 VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 4, 0), (64, 4, 2), (32, 8, 2),
-            (128, 2, 2), (256, 1, 2), (64, 4, 3), (64, 3, 3), (64, 2, 3)]
+            (128, 2, 2), (256, 1, 2)]
 
 
 @pytest.mark.parametrize("w", [W.detonation(nx=333, ny=7, steps=30).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
@@ -302,8 +302,8 @@ VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 
                                                                          bc_y="outflow", rk=3)],
                          ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67", "det-amod-rk3-333x7"])
 def test_launch_variants_give_bitwise_identical_results(w):
-    """Every compiled launch shape (collide-first with direct or LDS-staged stencil loads,
-    stream-first, and the LDS-resident tile) in both tile orders computes the same bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the
+    """Every compiled launch shape (collide-first with direct or LDS-staged stencil loads, and
+    stream-first) in both tile orders computes the same bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the
     column-band order is taken, with a ragged last tile column)."""
     F = {k: np.ascontiguousarray(v[:w.ny, :w.nx]) for k, v in (w.fields() if w.ny * w.nx < 1e5 else
                                                                   W.kh(n=2048).fields()).items()}
