@@ -9,10 +9,13 @@ the fused step kernel.  Reported beside it on the same GPU: the batched form (12
 the non-equilibrium loss over a 2048 x 256 detonation strip, 500 steps, checkpoints every
 50), each against the plain step's time per cell-update, and the reactive run with the
 single-relaxation-time collision (Sec. V, the MRT/SRT cost ratio of Table I), with the
-SSP Runge-Kutta time schemes, and between reflecting walls.  Prints one JSON line.
+SSP Runge-Kutta time schemes, and between reflecting walls; and the two small
+configurations (Sod 400 x 1, the detonation 8000 x 4) as whole runs with the oracle's rates
+beside them.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
                   [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk] [--no-walls]
+                  [--no-small]
                   [--launch TXxTY[l|s]:ORDER]   (fix the step's launch instead of autotuning it)
 """
 
@@ -174,6 +177,28 @@ def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
     good = (torch.isfinite(m["rho"]) & (m["T"] > 0)).cpu().numpy()
     ok = [bool(good[b.offsets[k]:b.offsets[k + 1]].all()) for k in range(len(spec.nx))]
     lost = [k for k in range(len(spec.nx)) if not ok[k]]
+    # steps 500..1500 timed alone (every instance is physical until about step 2000; the
+    # oracle goldens cover the first 1000), and the number of physical instances as the run
+    # goes on
+    b2 = lbkm.batch_from_spec(spec)
+    b2.set_launch(per_cu)
+    b2.step(chunk)                                 # captures the graph
+    torch.cuda.synchronize()
+    window = 1000
+    e0.record()
+    for _ in range(window // chunk):
+        b2.step(chunk)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_w = e0.elapsed_time(e1) / window
+    physical = {}
+    done = chunk + window
+    physical[done] = _physical_count(b2, spec)
+    while done < steps:
+        b2.step(chunk)
+        done += chunk
+        physical[done] = _physical_count(b2, spec)
+    b2.close()
     # the same instances as separate single-grid runs, one launch per instance and step
     sims = [lbkm.sim_from_workload(spec.instance(k)) for k in range(len(spec.nx))]
     for s_ in sims:
@@ -199,7 +224,79 @@ def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
             # instances whose temperature turned non-positive (the explicit scheme loses
             # stability near the driver when Pr approaches 5; the CPU oracle does the same)
             "instances_lost": {int(k): round(float(spec.Pr[k]), 3) for k in lost},
+            "physical_window": {"steps": [chunk, chunk + window], "ms_per_step": round(ms_w, 5),
+                                "mlups": round(b.total / (ms_w * 1e-3) / 1e6, 2),
+                                "hbm_frac": round(BYTES_PER_CELL * b.total / (ms_w * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "vs_plain_step_time_per_cell": round(ms_w * 1e6 / b.total / ns_per_cell_plain, 3)},
+            "physical_instances_after_step": {str(k): v for k, v in physical.items()},
             "separate_launches_mlups": round(b.total / (sep_ms * 1e-3) / 1e6, 2)}
+
+
+def _physical_count(b, spec):
+    import torch
+    m = b.moments()
+    good = (torch.isfinite(m["rho"]) & (m["T"] > 0)).cpu().numpy()
+    return int(sum(bool(good[b.offsets[k]:b.offsets[k + 1]].all()) for k in range(len(spec.nx))))
+
+
+def _oracle_rate(w, steps, threads):
+    """The oracle's cell-update rate (MLUPS) on `threads` host threads over `steps` steps of
+    workload w from its initial fields, after one untimed step."""
+    import numpy as np
+    import torch
+    import oracle
+    P = oracle.Params(dvm=oracle.DVM(*w.dvm), I=w.I, R=w.R, dx=w.dx, dy=w.dy, dt=w.dt, Q=w.Q,
+                      omega1=w.omega1, omega2=w.omega2, m=w.m, n=w.n, T_ig=w.T_ig, bc_x=w.bc_x, bc_y=w.bc_y)
+    tab = oracle.make_tables(P)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)) for k, v in w.fields().items()}
+    before = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        f = oracle.init_f(t["rho"], t["ux"], t["uy"], t["T"], P, tab)
+        f, lam = oracle.step(f, t["lam"], P, tab)
+        t0 = time.perf_counter()
+        f, lam = oracle.run(f, lam, P, tab, steps)
+        dt = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(before)
+    return w.nx * w.ny * steps / dt / 1e6, dt
+
+
+def bench_small_configs(ns_per_cell_plain, oracle_rates=True):
+    """The two small configurations, each as a whole run from its initial fields on the GPU
+    (launch shape autotuned first): Sod 400 x 1 for 2000 steps and the detonation 8000 x 4
+    for 20000 steps; beside them the oracle's rate on one host thread and on all of them,
+    over a bounded number of steps of the same run."""
+    import torch
+    from paper_1411_6697_amd import lbkm
+    from paper_1411_6697_amd import workloads as W
+    out = {}
+    for name, w, osteps in (("sod_400x1_2000_steps", W.sod(), 200),
+                            ("detonation_8000x4_20000_steps", W.detonation(), 20)):
+        s = lbkm.sim_from_workload(w)
+        launch = s.autotune()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(w.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cells = w.nx * w.ny
+        gbs = BYTES_PER_CELL * cells * w.steps / (ms * 1e-3) / 1e9
+        r = {"cells": cells, "steps": w.steps, "run_ms": round(ms, 3), "ms_per_step": round(ms / w.steps, 5),
+             "mlups": round(cells * w.steps / (ms * 1e-3) / 1e6, 2), "algorithmic_gbs": round(gbs, 1),
+             "hbm_frac": round(gbs / HBM_PEAK_GBS, 5), "launch": list(launch), "finite": bool(s.check())}
+        s.close()
+        if oracle_rates:
+            r1, d1 = _oracle_rate(w, osteps, 1)
+            ra, da = _oracle_rate(w, osteps, torch.get_num_threads())
+            r["oracle_mlups_1_thread"] = round(r1, 4)
+            r["oracle_mlups_all_threads"] = round(ra, 4)
+            r["oracle_threads"] = torch.get_num_threads()
+            r["oracle_sample"] = f"{osteps} steps of the same run after 1 untimed step ({d1:.1f} s, {da:.1f} s)"
+        out[name] = r
+    return out
 
 
 def bench_adjoint(ns_per_cell_plain):
@@ -267,6 +364,7 @@ def main():
     ap.add_argument("--no-srt", action="store_true")
     ap.add_argument("--no-rk", action="store_true")
     ap.add_argument("--no-walls", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="fix the KH step's launch instead of autotuning it: TXxTY[l|s]:ORDER, e.g. 64x4s:1 "
                          "(l = LDS-staged stencil, s = stream-first kernel, ORDER 1 = column bands); used to "
@@ -367,7 +465,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"kelvin_helmholtz_{w.nx}x{w.ny}_reactive_Q1_periodic",
-                   "nx": w.nx, "ny": w.ny, "dt": w.dt, "velocities": "D2V24",
+                   "nx": w.nx, "ny": w.ny, "dx": w.dx, "dt": w.dt, "velocities": "D2V24",
+                   "dvm_va_vb_vc_eta_a_eta_b_eta_c": list(w.dvm), "gamma": w.gamma, "Q": w.Q,
+                   "rates": "R_1..R_24 = %g (all equal)" % w.R[4] if len(set(w.R)) == 1 else list(w.R),
+                   "omega1_omega2": [w.omega1, w.omega2],
                    "launch": {"tile": [launch[0], launch[1]], "lds": launch[2], "column_bands": launch[3]},
                    "state_finite_after_run": bool(ok)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -386,6 +487,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(ns_cell)
+        torch.cuda.empty_cache()
+    if not args.no_small:
+        out["small_configs"] = bench_small_configs(ns_cell, oracle_rates=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

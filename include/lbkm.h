@@ -120,7 +120,10 @@ lbkm_status lbkm_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
  * library), or 2 / 3 launches for the Runge-Kutta schemes of lbkm_set_time_scheme; with
  * wall sides (lbkm_set_boundary) each launch is preceded by the fill of the ghost layers.
  * The library allocates, on first need and for the life of the context, the velocity planes
- * of the modification term, the third Runge-Kutta state and the ghost layers.  Errors:
+ * of the modification term, the third Runge-Kutta state and the ghost layers.  On grids of
+ * at most 262144 cells a call with n >= 64 replays a HIP graph of the launches of 64 steps,
+ * captured once per buffer parity and launch configuration on a library stream (the same
+ * kernels: results are bitwise those of n single steps).  Errors:
  * EINVAL for n < 0; ESTATE before buffers, parameters and fields are set; EDEVICE for a
  * failed launch or allocation. */
 lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n);

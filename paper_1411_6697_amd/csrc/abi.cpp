@@ -146,6 +146,8 @@ lbkm_status upload_consts(lbkm_ctx* ctx) {
 
 extern "C" {
 
+static void drop_step_graphs(lbkm_ctx* ctx);
+
 lbkm_status lbkm_create(const lbkm_grid* grid, void* hip_stream, lbkm_ctx** out) {
     if (!grid || !out) return LBKM_EINVAL;
     *out = nullptr;
@@ -180,6 +182,7 @@ lbkm_status lbkm_bind_buffers(lbkm_ctx* ctx, double* f_a, double* f_b, double* l
     if (pitch < ctx->grid.nx) return fail(ctx, LBKM_EINVAL, "pitch < nx");
     if ((int64_t)NV * pitch * ctx->grid.ny * 8 > 0xFFFFFFFFll)
         return fail(ctx, LBKM_EINVAL, "24 pitch ny doubles exceed 4 GiB (the kernels use 32-bit plane offsets)");
+    drop_step_graphs(ctx);             // replayed graphs hold the old buffer addresses
     ctx->f[0] = f_a;
     ctx->f[1] = f_b;
     ctx->lam[0] = lam_a;
@@ -293,6 +296,20 @@ static lbkm_status ghost_ready(lbkm_ctx* ctx) {
     return LBKM_OK;
 }
 
+// Grids up to kGraphCells cells are launch-bound: a call of at least kGraphSteps steps
+// replays a captured graph of kGraphSteps steps (an even number, so a replay ends on the
+// buffer parity it starts from) instead of launching every kernel from the host.
+constexpr int64_t kGraphSteps = 64;
+constexpr int64_t kGraphCells = 1 << 18;
+
+static void drop_step_graphs(lbkm_ctx* ctx) {
+    for (int p = 0; p < 2; ++p) {
+        if (ctx->step_exec[p]) (void)hipGraphExecDestroy(ctx->step_exec[p]);
+        ctx->step_exec[p] = nullptr;
+        ctx->step_key[p] = -1;
+    }
+}
+
 lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
@@ -324,27 +341,67 @@ lbkm_status lbkm_step(lbkm_ctx* ctx, int64_t n) {
         }
         return launch_step(ctx->d, var, flags, nx, ny, fi, fo, li, lo, ui, uo, ord, ctx->stream, bl, gb);
     };
-    for (int64_t k = 0; k < n; ++k) {
-        const int a = ctx->cur, b = 1 - a;
-        double *fa = ctx->f[a], *fb = ctx->f[b], *la = ctx->lam[a], *lb = ctx->lam[b];
-        double *ua = ctx->u[a], *ub = ctx->u[b];
-        // forward Euler, and the first stage of both Runge-Kutta schemes: state b = E(state a)
-        hipError_t e = stage(fa, fb, la, lb, ua, ub, nullptr);
-        if (e == hipSuccess && ctx->rk == 2) {
-            // f^{n+1} = f^n / 2 + E(g_1) / 2, written over f^n
-            const Blend bl{nullptr, nullptr, 0.5, 0.5};
-            e = stage(fb, fa, lb, la, ub, ua, &bl);
-        } else if (e == hipSuccess && ctx->rk == 3) {
-            // g_2 = 3/4 f^n + 1/4 E(g_1); f^{n+1} = 1/3 f^n + 2/3 E(g_2), written over f^n
-            const Blend b2{fa, la, 0.75, 0.25};
-            e = stage(fb, ctx->f3, lb, ctx->lam3, ub, ctx->u3, &b2);
-            const Blend b3{nullptr, nullptr, 1.0 / 3.0, 2.0 / 3.0};
-            if (e == hipSuccess) e = stage(ctx->f3, fa, ctx->lam3, la, ctx->u3, ua, &b3);
+    // `count` steps from buffer parity `a0` enqueued on stream `s`; returns the final parity
+    auto issue = [&](int64_t count, int a0, hipStream_t s, int& a_end) {
+        hipStream_t keep = ctx->stream;
+        ctx->stream = s;
+        hipError_t e = hipSuccess;
+        int a = a0;
+        for (int64_t k = 0; k < count && e == hipSuccess; ++k) {
+            const int b = 1 - a;
+            double *fa = ctx->f[a], *fb = ctx->f[b], *la = ctx->lam[a], *lb = ctx->lam[b];
+            double *ua = ctx->u[a], *ub = ctx->u[b];
+            // forward Euler, and the first stage of both Runge-Kutta schemes: state b = E(state a)
+            e = stage(fa, fb, la, lb, ua, ub, nullptr);
+            if (e == hipSuccess && ctx->rk == 2) {
+                // f^{n+1} = f^n / 2 + E(g_1) / 2, written over f^n
+                const Blend bl{nullptr, nullptr, 0.5, 0.5};
+                e = stage(fb, fa, lb, la, ub, ua, &bl);
+            } else if (e == hipSuccess && ctx->rk == 3) {
+                // g_2 = 3/4 f^n + 1/4 E(g_1); f^{n+1} = 1/3 f^n + 2/3 E(g_2), written over f^n
+                const Blend b2{fa, la, 0.75, 0.25};
+                e = stage(fb, ctx->f3, lb, ctx->lam3, ub, ctx->u3, &b2);
+                const Blend b3{nullptr, nullptr, 1.0 / 3.0, 2.0 / 3.0};
+                if (e == hipSuccess) e = stage(ctx->f3, fa, ctx->lam3, la, ctx->u3, ua, &b3);
+            }
+            if (ctx->rk == 1) a = b;
         }
-        if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
-        if (ctx->rk == 1) ctx->cur = b;
-        ++ctx->steps;
+        ctx->stream = keep;
+        a_end = a;
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    int64_t done = 0;
+    if ((int64_t)nx * ny <= kGraphCells && n >= kGraphSteps) {
+        const int p = ctx->cur;
+        const int64_t key = ((((int64_t)var * 2 + ord) * 64 + flags) * 4 + ctx->rk) * 2 + (walls ? 1 : 0);
+        if (ctx->step_key[p] != key) {
+            if (ctx->step_exec[p]) (void)hipGraphExecDestroy(ctx->step_exec[p]);
+            ctx->step_exec[p] = nullptr;
+            ctx->step_key[p] = -1;
+            if (!ctx->step_cap) e = hipStreamCreateWithFlags(&ctx->step_cap, hipStreamNonBlocking);
+            hipGraph_t g = nullptr;
+            if (e == hipSuccess) e = hipStreamBeginCapture(ctx->step_cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                int a_end = p;
+                const hipError_t le = issue(kGraphSteps, p, ctx->step_cap, a_end);
+                e = hipStreamEndCapture(ctx->step_cap, &g);
+                if (e == hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&ctx->step_exec[p], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(ctx, e, "step graph capture");
+            ctx->step_key[p] = key;
+        }
+        for (; done + kGraphSteps <= n && e == hipSuccess; done += kGraphSteps)
+            e = hipGraphLaunch(ctx->step_exec[p], ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "step graph launch");
     }
+    int a_end = ctx->cur;
+    e = issue(n - done, ctx->cur, ctx->stream, a_end);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step kernel");
+    ctx->cur = a_end;
+    ctx->steps += n;
     ctx->u_valid = amod;            // a step without A_hat does not write the velocity planes
     return LBKM_OK;
 }
@@ -572,6 +629,8 @@ const char* lbkm_last_error(const lbkm_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 lbkm_status lbkm_destroy(lbkm_ctx* ctx) {
     if (!ctx) return LBKM_EINVAL;
+    drop_step_graphs(ctx);
+    if (ctx->step_cap) (void)hipStreamDestroy(ctx->step_cap);
     destroy_extras(ctx);
     if (ctx->d) (void)hipFree(ctx->d);
     if (ctx->partials) (void)hipFree(ctx->partials);

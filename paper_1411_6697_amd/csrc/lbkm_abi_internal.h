@@ -45,6 +45,11 @@ struct lbkm_ctx {
     double* gbuf = nullptr;            // ghost layers of the wall sides [27][4][2][max(nx, ny)]
     double* adj_scratch = nullptr;     // adjoint step: U, W planes and parameter partials
     int64_t adj_scratch_n = 0;
+    // small grids: the launches of kGraphSteps steps captured once per buffer parity and
+    // launch configuration (step_key) and replayed by lbkm_step
+    hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+    int64_t step_key[2] = {-1, -1};
+    hipStream_t step_cap = nullptr;
     std::string err;
 };
 

@@ -342,6 +342,33 @@ def test_autotune_restores_state_and_keeps_results():
         assert torch.equal(ma[k], mb[k]), k
 
 
+@pytest.mark.parametrize("case", ["euler-amod", "rk3", "walls", "srt"])
+def test_graph_replay_equals_single_steps(case):
+    """lbkm_step replays a captured graph of 64 steps on small grids when called with n >= 64;
+    200 steps in one call (three replays and 8 single steps, across both buffer parities)
+    equal 200 calls of one step bitwise, for forward Euler with A_hat, SSP-RK3, wall sides
+    (ghost-layer fills inside the graph) and the SRT form."""
+    w = W.detonation(nx=333, ny=7, steps=200).with_(R=W.rates(100.0, r8=200.0, r9=150.0), bc_y="outflow")
+    if case == "rk3":
+        w = w.with_(rk=3)
+    elif case == "walls":
+        w = w.with_(walls={"y_lo": ("reflect",), "y_hi": ("reflect",)})
+    elif case == "srt":
+        w = w.with_(tau=1.0 / 100.0)
+    a = _lbkm().sim_from_workload(w)
+    a.step(7)
+    a.step(200)
+    b = _lbkm().sim_from_workload(w)
+    for _ in range(207):
+        b.step(1)
+    ma, mb = a.moments(), b.moments()
+    torch.cuda.synchronize()
+    assert a.step_count() == b.step_count() == 207
+    for k in ma:
+        assert torch.equal(ma[k], mb[k]), (case, k)
+    assert a.check()
+
+
 def test_larger_pitch_gives_bitwise_identical_results():
     w = W.sod(nx=200, steps=100)
     _, a = _gpu(w, 100)
