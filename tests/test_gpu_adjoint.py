@@ -271,12 +271,12 @@ def test_full_size_gradient_matches_central_differences():
     """The 2048 x 256 strip, 500 steps, checkpoints every 50: d L / d theta_k against
     central differences of the GPU forward run, (L(theta + h theta_k e_k) -
     L(theta - h theta_k e_k)) / (2 h theta_k) for h = 1e-5 ... 1e-8 (printed).  The bar,
-    relative error <= 1e-5, applies at h = 1e-7.  Larger steps are not usable for R_5 and
-    R_8: with u_y noise of 1e-3 the planes with v_iy = 0 vary only at the 1e-6 scale, and
-    a relative change of R_5 or R_8 above about 1e-6 moves minmod selections across their
-    switch points, where the discrete map has kinks (the finite differences converge to
-    the adjoint value as h decreases).  The initial-field gradients are compared with the
-    oracle's at reduced size instead, for the same reason."""
+    relative error <= 1e-5, applies at h = 1e-6 for R_9, R_21, Q, omega_1 and omega_2 (about
+    5e-8 there) and at h = 1e-7 for R_5 and R_8 (1.6e-5 and 1.5e-5 at h = 1e-6, 3e-6 at
+    h = 1e-7): with u_y noise of 1e-3 the planes with v_iy = 0 vary only at the 1e-6 scale,
+    and a relative change of R_5 or R_8 above about 1e-6 moves minmod selections across
+    their switch points, where the discrete map has kinks (the finite differences converge
+    to the adjoint value as h decreases)."""
     w = W.adjoint_strip()
     s, L, gth, _ = _gpu_run_gradient(w, w.steps, 50)
     assert np.isfinite(L) and L > 0
@@ -291,4 +291,65 @@ def test_full_size_gradient_matches_central_differences():
             fd = (_loss_at(s, w, tp, F) - _loss_at(s, w, tm, F)) / (2 * h * th[k])
             rel[h] = abs(fd - gth[k]) / abs(gth[k])
         print("theta", k, "adjoint", gth[k], {h: f"{v:.1e}" for h, v in rel.items()}, flush=True)
-        assert rel[1e-7] <= 1e-5, (k, gth[k], rel)
+        assert rel[1e-7 if k in (4, 7) else 1e-6] <= 1e-5, (k, gth[k], rel)
+
+
+def _loss_from_fields(s, w, F):
+    s.set_theta(_theta(w), w.gamma, w.m, w.n, w.T_ig)
+    s.init_fields(F["rho"], F["ux"], F["uy"], F["T"], F["lam"])
+    s.step(w.steps)
+    f, _ = s.get_state()
+    loss, _ = s.tne_loss(f, grad=False)
+    return float(loss)
+
+
+def test_full_size_initial_field_gradients_match_central_differences():
+    """The 2048 x 256 strip, 500 steps, checkpoints every 50: the gradient with respect to the
+    initial rho, u_x, u_y, T and lambda (through the adjoint of the initialisation
+    f = M^-1 f_hat^eq), sum(dL/dF * delta) along a direction delta per field, against central
+    differences (L(F + h delta) - L(F - h delta)) / (2 h) of the GPU forward run for
+    h = 1e-6, 1e-7, 1e-8 (printed).
+
+    The strip's white u_y noise leaves neighbouring differences of the distributions at 1e-6
+    of their size or less away from the front, and the initial lambda is exactly 0 or 1, so a
+    perturbation of those cells moves minmod selections (and the ignition gate) across their
+    switch points at any usable h: for a random relative rho perturbation the finite
+    differences miss by 3e-2, 8e-3, 2e-3 at h = 1e-6, 1e-7, 1e-8.  The directions are
+    therefore:
+      rho scaled uniformly (minmod is homogeneous of degree one, so only the pressure
+        dependence of the reaction rate moves the state off that scaling): 1e-5 at h = 1e-6;
+      u_y's noise scaled by a bump at the front (x = 200 cells, width 4; y-differences scale
+        alike in a column): 1e-5 at h = 1e-6;
+      rho, T and u_x bumps at the front: the differences converge to the adjoint value as h
+        shrinks (the kinks they cross become fewer), 1e-5 at h = 1e-8 (rho, T) and 5e-5
+        (u_x);
+      lambda on the unburnt cells at the front: converging, 5e-4 at h = 1e-8.
+    The initial-field gradients are matched to the oracle's reverse-mode derivative at 1e-8
+    on a reduced strip (test_checkpointed_run_gradient_matches_oracle_autograd)."""
+    w = W.adjoint_strip()
+    F = w.fields()
+    s, L, _, gf = _gpu_run_gradient(w, w.steps, 50, F)
+    x = np.arange(w.nx)[None, :] * np.ones((w.ny, 1))
+    bump = lambda c, sig: np.exp(-((x - c) / sig) ** 2)
+    dirs = {"rho": F["rho"],
+            "rho_front": F["rho"] * bump(200.0, 4.0),
+            "T": F["T"] * bump(200.0, 4.0),
+            "ux": 0.5 * bump(200.0, 4.0),
+            "uy": F["uy"] * bump(200.0, 4.0),
+            "lam": np.where(F["lam"] < 0.5, bump(202.0, 3.0), 0.0)}
+    for name, d in dirs.items():
+        k = name.split("_")[0]
+        want = float(np.sum(gf[k] * d))
+        rel = {}
+        for h in (1e-6, 1e-7, 1e-8):
+            Fp, Fm = dict(F), dict(F)
+            Fp[k] = F[k] + h * d
+            Fm[k] = F[k] - h * d
+            fd = (_loss_from_fields(s, w, Fp) - _loss_from_fields(s, w, Fm)) / (2 * h)
+            rel[h] = abs(fd - want) / abs(want)
+        print("d/d" + name, "adjoint", want, {h: f"{v:.1e}" for h, v in rel.items()}, flush=True)
+        bar = {"rho": (1e-6, 1e-5), "uy": (1e-6, 1e-5), "rho_front": (1e-8, 1e-5), "T": (1e-8, 1e-5),
+               "ux": (1e-8, 5e-5), "lam": (1e-8, 5e-4)}[name]
+        assert rel[bar[0]] <= bar[1], (name, want, rel)
+        if bar[0] == 1e-8:
+            assert rel[1e-8] < rel[1e-7] < rel[1e-6], (name, rel)     # converging as h shrinks
