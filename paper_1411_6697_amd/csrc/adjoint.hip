@@ -316,10 +316,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
         {
             const double l_m2 = lam[row + wrap(x - 2, nx, c->bc_x)], l_m1 = lam[row + xm];
             const double l_p1 = lam[row + xp], l_p2 = lam[row + wrap(x + 2, nx, c->bc_x)];
-            dlx = (m.ux > 0.0 ? nnd_pos(l_m2, l_m1, lm, l_p1) : nnd_neg(l_m1, lm, l_p1, l_p2)) * c->inv_dx;
+            dlx = nnd_upwind(m.ux > 0.0, l_m2, l_m1, lm, l_p1, l_p2) * c->inv_dx;
             const double b_m2 = lam[(int64_t)wrap(y - 2, ny, c->bc_y) * nx + x], b_m1 = lam[(int64_t)ym * nx + x];
             const double b_p1 = lam[(int64_t)yp * nx + x], b_p2 = lam[(int64_t)wrap(y + 2, ny, c->bc_y) * nx + x];
-            dly = (m.uy > 0.0 ? nnd_pos(b_m2, b_m1, lm, b_p1) : nnd_neg(b_m1, lm, b_p1, b_p2)) * c->inv_dy;
+            dly = nnd_upwind(m.uy > 0.0, b_m2, b_m1, lm, b_p1, b_p2) * c->inv_dy;
         }
 
         // ---- reverse sweep --------------------------------------------------------
@@ -586,38 +586,60 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
     const double hb1 = W[3 * plane + at], hb2 = W[4 * plane + at], hb3 = W[5 * plane + at],
                  hb4 = W[6 * plane + at];
 
-    // transposed streaming of f: adv_i = v_ix D_x f_i + v_iy D_y f_i, adjoint -dt a_i
+    // transposed streaming of f: adv_i = v_ix D_x f_i + v_iy D_y f_i, adjoint -dt a_i.  The
+    // loads of plane i+1's stencils are issued before plane i is differenced (the scheduling
+    // barrier keeps them there), so each plane's memory latency hides behind the previous
+    // plane's arithmetic; all 24 updates are formed before any store into af0, which would
+    // otherwise hold the following loads behind it.
+    struct PlaneLoads {
+        double fx[5], ax[5], fy[5], ay[5];   // f and a^{n+1} at offsets -2..2 along x and y
+    };
+    auto load_plane = [&](int i, PlaneLoads& p) {
+        const uint32_t so = (uint32_t)i * pb;
+        const int d = i & 7;
+        if (DUX[d] != 0) {
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double vg = c->vg[g];
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int i = 8 * g + d;
-            const uint32_t so = (uint32_t)i * pb;
-            double acc = 0.0;
-            if (DUX[d] != 0) {
-                double fv[5], av[5];
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    fv[t] = ld(Fb, so, bx[t]);
-                    av[t] = AX.val[t] * ld(Ab, so, bx[t]);
-                }
-                acc += vg * DUX[d] * c->inv_dx * nnd_t(AX, fv, av, DUX[d]);
+            for (int t = 0; t < 5; ++t) {
+                p.fx[t] = ld(Fb, so, bx[t]);
+                p.ax[t] = ld(Ab, so, bx[t]);
             }
-            if (DUY[d] != 0) {
-                double fv[5], av[5];
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    fv[t] = ld(Fb, so, by[t]);
-                    av[t] = AY.val[t] * ld(Ab, so, by[t]);
-                }
-                acc += vg * DUY[d] * c->inv_dy * nnd_t(AY, fv, av, DUY[d]);
-            }
-            const double vx = vg * DUX[d], vy = vg * DUY[d];
-            const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + c->eta2[g]) * hb4;
-            const double upd = ld(Ab, so, bc) - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
-            st(Ob, so, bc, ld(Ob, so, bc) + upd);
         }
+        if (DUY[d] != 0) {
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                p.fy[t] = ld(Fb, so, by[t]);
+                p.ay[t] = ld(Ab, so, by[t]);
+            }
+        }
+    };
+    double upd[NV];
+    PlaneLoads cur, nxt;
+    load_plane(0, cur);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i + 1 < NV) load_plane(i + 1, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        const int g = i / 8, d = i % 8;
+        const double vg = c->vg[g];
+        double acc = 0.0, a_c = 0.0;          // a_c: a^{n+1} of this cell (offset 0 of a stencil)
+        if (DUX[d] != 0) {
+            double av[5];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) av[t] = AX.val[t] * cur.ax[t];
+            acc += vg * DUX[d] * c->inv_dx * nnd_t(AX, cur.fx, av, DUX[d]);
+            a_c = cur.ax[2];
+        }
+        if (DUY[d] != 0) {
+            double av[5];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) av[t] = AY.val[t] * cur.ay[t];
+            acc += vg * DUY[d] * c->inv_dy * nnd_t(AY, cur.fy, av, DUY[d]);
+            a_c = cur.ay[2];
+        }
+        const double vx = vg * DUX[d], vy = vg * DUY[d];
+        const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + c->eta2[g]) * hb4;
+        upd[i] = a_c - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
+        cur = nxt;
     }
 
     // transposed advection of lambda: D lambda at cell j is upwinded by the sign of u(j)
@@ -634,6 +656,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
         return inv * (nnd_t(A, lv, ap, +1) + nnd_t(A, lv, an, -1));
     };
     const double lb = lam_t(AX, ox, U + plane, c->inv_dx) + lam_t(AY, oy, U + 2 * plane, c->inv_dy);
+    // add the collision part that k_adj_local wrote: 24 loads in one burst, then the stores
+#pragma unroll
+    for (int i = 0; i < NV; ++i) upd[i] = ld(Ob, (uint32_t)i * pb, bc) + upd[i];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) st(Ob, (uint32_t)i * pb, bc, upd[i]);
     al0[at] += lb;
 }
 

@@ -90,11 +90,22 @@ __device__ __forceinline__ bool wait_counter(const uint32_t* flags, int nb, int 
     return false;
 }
 
+// Constants of the streaming part, read once before the step loop: inside it every
+// step's device-scope fence counts as a write to all memory, after which the compiler
+// reads the constants block with vector loads, each one a wait that also drains the
+// stencil loads in flight.
+struct StreamConsts {
+    double dt, inv_dx, half_inv_dx;
+    double vg[3];                               // speeds of the three groups
+    double wx[3];                               // Courant numbers dt v_g / dx of the groups
+};
+
 // one step of one cell of a 1D instance (x-derivatives only; y-differences are zero)
 template <bool AMOD, bool CHEM, bool GEXP>
-__device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const BatchInst* __restrict__ I, int lo,
-                                        int hi, int j, const Soa& F, const Soa& G, const Soa& L, const Soa& Lo,
-                                        const Soa& Ui, const Soa& Uo) {
+__device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const StreamConsts& k,
+                                        const BatchInst* __restrict__ I, int lo, int hi, int j, const Soa& F,
+                                        const Soa& G, const Soa& L, const Soa& Lo, const Soa& Ui,
+                                        const Soa& Uo) {
     const uint32_t oc = (uint32_t)j * 8u;
     const uint32_t om2 = (uint32_t)max(j - 2, lo) * 8u, om1 = (uint32_t)max(j - 1, lo) * 8u;
     const uint32_t op1 = (uint32_t)min(j + 1, hi) * 8u, op2 = (uint32_t)min(j + 2, hi) * 8u;
@@ -106,8 +117,8 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
         if (AMOD && I->amod) {
             // the neighbours' velocities, written by the previous step (or k_velocity)
             const uint32_t up = opaque(Ui.plane_bytes);
-            gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * c->half_inv_dx;
-            gyx = (ld(Ui, up, op1) - ld(Ui, up, om1)) * c->half_inv_dx;
+            gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * k.half_inv_dx;
+            gyx = (ld(Ui, up, op1) - ld(Ui, up, om1)) * k.half_inv_dx;
         }
         double f[NV];
         load_cell(F, oc, f);
@@ -121,31 +132,62 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Batc
         local_source<CHEM, GEXP>(c, c->mat, lam, A8, A9, m, h, src, dlam, I->R);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const double dt = c->dt, idx_ = c->inv_dx;
+    const double dt = k.dt, idx_ = k.inv_dx;
     const uint32_t pb = opaque(F.plane_bytes);
-    VelAcc va;                                  // velocity of the new state (for A_hat)
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        const double v = c->vg[g];
-        const double wx = dt * v * idx_;              // Courant number of the group
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const uint32_t so = (uint32_t)(8 * g + d) * pb;
-            const double f0 = ld(F, so, oc);
-            double a = f0;
-            if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, om2), ld(F, so, om1), f0, ld(F, so, op1)), a);
-            if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, om1), f0, ld(F, so, op1), ld(F, so, op2)), a);
-            double out = fma(dt, src[8 * g + d], a);
-            if (AMOD) vel_add(va, c, g, d, out);
-            st(G, so, oc, out);
+    // The input and output buffers trade places from step to step, so the compiler cannot
+    // tell that a store of plane i leaves plane i+1's stencil unchanged, and would issue
+    // those loads only after the store: one memory round trip per plane.  Plane i+1's loads
+    // (and, with the last plane, lambda's stencil) are therefore issued before plane i is
+    // differenced and stored, and the scheduling barrier keeps them there.
+    struct PlaneLoads {
+        double v[5];                            // offsets -2..2 (those the upwind side uses)
+    };
+    auto load_plane = [&](int i, PlaneLoads& p) {
+        const uint32_t so = (uint32_t)i * pb;
+        const int d = i & 7;
+        p.v[2] = ld(F, so, oc);
+        if (DUX[d] > 0) {
+            p.v[0] = ld(F, so, om2);
+            p.v[1] = ld(F, so, om1);
+            p.v[3] = ld(F, so, op1);
         }
+        if (DUX[d] < 0) {
+            p.v[1] = ld(F, so, om1);
+            p.v[3] = ld(F, so, op1);
+            p.v[4] = ld(F, so, op2);
+        }
+    };
+    VelAcc va;                                  // velocity of the new state (for A_hat)
+    PlaneLoads cur, nxt;
+    double lm2 = 0.0, lm1 = 0.0, lp1 = 0.0, lp2 = 0.0;
+    load_plane(0, cur);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i + 1 < NV) {
+            load_plane(i + 1, nxt);
+        } else {
+            lm2 = ld(L, 0u, om2);
+            lm1 = ld(L, 0u, om1);
+            lp1 = ld(L, 0u, op1);
+            lp2 = ld(L, 0u, op2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int g = i / 8, d = i % 8;
+        const double wx = k.wx[g];                    // Courant number of the group
+        const double f0 = cur.v[2];
+        double a = f0;
+        if (DUX[d] > 0) a = fma(-wx, nnd_pos(cur.v[0], cur.v[1], f0, cur.v[3]), a);
+        if (DUX[d] < 0) a = fma(wx, nnd_neg(cur.v[1], f0, cur.v[3], cur.v[4]), a);
+        double out = fma(dt, src[i], a);
+        if (AMOD) vel_add(va, k.vg[g], d, out);
+        st(G, (uint32_t)i * pb, oc, out);
+        cur = nxt;
     }
     if (AMOD) {
         st(Uo, 0u, oc, va.jx / va.r);
         st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
     }
-    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, om2), ld(L, 0u, om1), lam, ld(L, 0u, op1))
-                                    : nnd_neg(ld(L, 0u, om1), lam, ld(L, 0u, op1), ld(L, 0u, op2));
+    const double dlx = nnd_upwind(m.ux > 0.0, lm2, lm1, lam, lp1, lp2);
     st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
 }
 
@@ -166,6 +208,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
     __shared__ int32_t stop;
     // the descriptors are swapped after every step (selecting them by step parity inside
     // the loop would turn them into per-lane values)
+    StreamConsts k;
+    k.dt = c->dt;
+    k.inv_dx = c->inv_dx;
+    k.half_inv_dx = c->half_inv_dx;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        k.vg[g] = c->vg[g];
+        k.wx[g] = c->dt * c->vg[g] * c->inv_dx;
+    }
     Soa F = soa(parity ? f1 : f0, c->plane), G = soa(parity ? f0 : f1, c->plane);
     Soa L = soa(parity ? l1 : l0, 0), Lo = soa(parity ? l0 : l1, 0);
     Soa Ui = soa(parity ? u1 : u0, c->plane), Uo = soa(parity ? u0 : u1, c->plane);
@@ -188,7 +239,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
             // uniform trip count; the tail is masked
             for (int base = S.begin; base < S.end; base += kBatchThreads) {
                 const int j = base + (int)threadIdx.x;
-                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, j, F, G, L, Lo, Ui, Uo);
+                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, k, I, S.lo, S.hi, j, F, G, L, Lo, Ui, Uo);
             }
         }
         // The barrier orders every thread's stores before thread 0's release (cumulative),

@@ -189,10 +189,13 @@ __device__ __forceinline__ Macro macro_of(const Blocks& h, double DI) {
 struct VelAcc {
     double r = 0.0, jx = 0.0, jy = 0.0;
 };
-__device__ __forceinline__ void vel_add(VelAcc& a, const Consts* __restrict__ c, int g, int d, double v) {
+__device__ __forceinline__ void vel_add(VelAcc& a, double vg, int d, double v) {
     a.r += v;
-    if (DUX[d] != 0) a.jx = fma(DUX[d] > 0 ? c->vg[g] : -c->vg[g], v, a.jx);
-    if (DUY[d] != 0) a.jy = fma(DUY[d] > 0 ? c->vg[g] : -c->vg[g], v, a.jy);
+    if (DUX[d] != 0) a.jx = fma(DUX[d] > 0 ? vg : -vg, v, a.jx);
+    if (DUY[d] != 0) a.jy = fma(DUY[d] > 0 ? vg : -vg, v, a.jy);
+}
+__device__ __forceinline__ void vel_add(VelAcc& a, const Consts* __restrict__ c, int g, int d, double v) {
+    vel_add(a, c->vg[g], d, v);
 }
 
 // minmod: the argument of smaller magnitude if both have the same strict sign, else 0.
@@ -213,6 +216,18 @@ __device__ __forceinline__ double nnd_pos(double fm2, double fm1, double f0, dou
 __device__ __forceinline__ double nnd_neg(double fm1, double f0, double fp1, double fp2) {
     const double d = fp1 - f0;
     return fma(-0.5, minmod(d, fp2 - fp1) - minmod(f0 - fm1, d), d);
+}
+
+// The NND difference upwinded by the sign of a velocity that varies from cell to cell
+// (u > 0: the positive-speed form, else the negative one), from the five stencil values.
+// Both forms are evaluated and one is selected, so the caller loads the whole stencil
+// unconditionally: a wave whose lanes differ in that sign then waits for one set of loads,
+// not for one set per side.
+__device__ __forceinline__ double nnd_upwind(bool pos, double fm2, double fm1, double f0, double fp1,
+                                             double fp2) {
+    const double a = nnd_pos(fm2, fm1, f0, fp1);
+    const double b = nnd_neg(fm1, f0, fp1, fp2);
+    return pos ? a : b;
 }
 
 // Cochran increment of lambda over one step, p frozen (exact solution of the Bernoulli

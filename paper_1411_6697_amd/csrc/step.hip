@@ -256,10 +256,8 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
         }
         const uint32_t sl = GH ? NV * Gb.plane_bytes : 0u;
         auto lat = [&](uint32_t off, int k) { return sld<GH>(L, 0u, off, Gb, sl, gh, k); };
-        const double dlx = (m.ux > 0.0) ? nnd_pos(lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2))
-                                        : nnd_neg(lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
-        const double dly = (m.uy > 0.0) ? nnd_pos(lat(s.ym2, 4), lat(s.ym1, 5), lam, lat(s.yp1, 6))
-                                        : nnd_neg(lat(s.ym1, 5), lam, lat(s.yp1, 6), lat(s.yp2, 7));
+        const double dlx = nnd_upwind(m.ux > 0.0, lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
+        const double dly = nnd_upwind(m.uy > 0.0, lat(s.ym2, 4), lat(s.ym1, 5), lam, lat(s.yp1, 6), lat(s.yp2, 7));
         double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
         if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
         st_stream(Lo, 0u, s.c, lnew);
@@ -371,9 +369,8 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
                 st_stream(Uo, 0u, out_off, va.jx / va.r);
                 st_stream(Uo, opaque(Uo.plane_bytes), out_off, va.jy / va.r);
             }
-            const double dlx = (m.ux > 0.0) ? nnd_pos(q[-2], q[-1], f0, q[1]) : nnd_neg(q[-1], f0, q[1], q[2]);
-            const double dly = (m.uy > 0.0) ? nnd_pos(q[-2 * P::PW], q[-P::PW], f0, q[P::PW])
-                                            : nnd_neg(q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
+            const double dlx = nnd_upwind(m.ux > 0.0, q[-2], q[-1], f0, q[1], q[2]);
+            const double dly = nnd_upwind(m.uy > 0.0, q[-2 * P::PW], q[-P::PW], f0, q[P::PW], q[2 * P::PW]);
             double lnew = f0 + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
             if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, out_off), bl.b * lnew);
             st_stream(Lo, 0u, out_off, lnew);
@@ -484,10 +481,10 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
             st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
         }
     }
-    const double dlx = (m.ux > 0.0) ? nnd_pos(ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1))
-                                    : nnd_neg(ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
-    const double dly = (m.uy > 0.0) ? nnd_pos(ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1))
-                                    : nnd_neg(ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1), ld(L, 0u, s.yp2));
+    const double dlx = nnd_upwind(m.ux > 0.0, ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1),
+                                  ld(L, 0u, s.xp2));
+    const double dly = nnd_upwind(m.uy > 0.0, ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1),
+                                  ld(L, 0u, s.yp2));
     double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
     if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
     st_stream(Lo, 0u, s.c, lnew);
