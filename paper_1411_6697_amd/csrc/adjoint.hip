@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                                                            double* __restrict__ af0, double* __restrict__ al0,
                                                            double* __restrict__ Wout, double* __restrict__ part) {
     __shared__ double sg[kNumLds][kAdjThreads];           // per-thread parameter gradients
-    const int nx = c->nx, ny = c->ny;
+    const int nx = ro(c->nx), ny = ro(c->ny);
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     const int tid = (int)threadIdx.x;
     const int64_t plane = (int64_t)nx * ny;
@@ -286,45 +286,50 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
 
     if (x < nx) {
         const int64_t at = (int64_t)y * nx + x;
-        const double dt = c->dt, I = c->I, DI = c->DI, D = 2.0;
+        const double dt = ro(c->dt), I = ro(c->I), DI = ro(c->DI), D = 2.0;
+        // Every load of the cell is issued first, in one burst: at one wave per SIMD each
+        // separate wait would be exposed in full.
+        const int bcx = ro(c->bc_x), bcy = ro(c->bc_y);
+        const int xp = wrap(x + 1, nx, bcx), xm = wrap(x - 1, nx, bcx);
+        const int yp = wrap(y + 1, ny, bcy), ym = wrap(y - 1, ny, bcy);
+        const int xp2 = wrap(x + 2, nx, bcx), xm2 = wrap(x - 2, nx, bcx);
+        const int yp2 = wrap(y + 2, ny, bcy), ym2 = wrap(y - 2, ny, bcy);
+        const int64_t row = (int64_t)y * nx;
+        const double* Ux = U + plane;
+        const double* Uy = U + 2 * plane;
+        double v[NV], sbar[NV];
+        load_dense(f, plane, at, v);
+        load_dense(af1, plane, at, sbar);
+        const double lm = lam[at];
+        const double beta = al1[at];
+        const double ux_xp = Ux[row + xp], ux_xm = Ux[row + xm], uy_xp = Uy[row + xp], uy_xm = Uy[row + xm];
+        const double ux_yp = Ux[(int64_t)yp * nx + x], ux_ym = Ux[(int64_t)ym * nx + x];
+        const double uy_yp = Uy[(int64_t)yp * nx + x], uy_ym = Uy[(int64_t)ym * nx + x];
+        const double l_m2 = lam[row + xm2], l_m1 = lam[row + xm], l_p1 = lam[row + xp], l_p2 = lam[row + xp2];
+        const double b_m2 = lam[(int64_t)ym2 * nx + x], b_m1 = lam[(int64_t)ym * nx + x];
+        const double b_p1 = lam[(int64_t)yp * nx + x], b_p2 = lam[(int64_t)yp2 * nx + x];
+        __builtin_amdgcn_sched_barrier(0);
+
         Blocks h;
         {
-            double v[NV];
-            load_dense(f, plane, at, v);
             Blocks sb;
             to_combos(v, sb);
             forward(c->mat, sb, h);
         }
         const Macro m = macro_of(h, DI);
         const double h4 = h.ee[1];
-        const double lm = lam[at];
-        const double beta = al1[at];
 
         // velocity gradients (central differences over the boundary rule)
-        const int xp = wrap(x + 1, nx, c->bc_x), xm = wrap(x - 1, nx, c->bc_x);
-        const int yp = wrap(y + 1, ny, c->bc_y), ym = wrap(y - 1, ny, c->bc_y);
-        const double* Ux = U + plane;
-        const double* Uy = U + 2 * plane;
-        const int64_t row = (int64_t)y * nx;
-        const double dux_dx = (Ux[row + xp] - Ux[row + xm]) * c->half_inv_dx;
-        const double duy_dx = (Uy[row + xp] - Uy[row + xm]) * c->half_inv_dx;
-        const double dux_dy = (Ux[(int64_t)yp * nx + x] - Ux[(int64_t)ym * nx + x]) * c->half_inv_dy;
-        const double duy_dy = (Uy[(int64_t)yp * nx + x] - Uy[(int64_t)ym * nx + x]) * c->half_inv_dy;
+        const double dux_dx = (ux_xp - ux_xm) * ro(c->half_inv_dx);
+        const double duy_dx = (uy_xp - uy_xm) * ro(c->half_inv_dx);
+        const double dux_dy = (ux_yp - ux_ym) * ro(c->half_inv_dy);
+        const double duy_dy = (uy_yp - uy_ym) * ro(c->half_inv_dy);
 
         // NND derivatives of lambda at this cell, upwind by the sign of u (forward values)
-        double dlx, dly;
-        {
-            const double l_m2 = lam[row + wrap(x - 2, nx, c->bc_x)], l_m1 = lam[row + xm];
-            const double l_p1 = lam[row + xp], l_p2 = lam[row + wrap(x + 2, nx, c->bc_x)];
-            dlx = nnd_upwind(m.ux > 0.0, l_m2, l_m1, lm, l_p1, l_p2) * c->inv_dx;
-            const double b_m2 = lam[(int64_t)wrap(y - 2, ny, c->bc_y) * nx + x], b_m1 = lam[(int64_t)ym * nx + x];
-            const double b_p1 = lam[(int64_t)yp * nx + x], b_p2 = lam[(int64_t)wrap(y + 2, ny, c->bc_y) * nx + x];
-            dly = nnd_upwind(m.uy > 0.0, b_m2, b_m1, lm, b_p1, b_p2) * c->inv_dy;
-        }
+        const double dlx = nnd_upwind(m.ux > 0.0, l_m2, l_m1, lm, l_p1, l_p2) * ro(c->inv_dx);
+        const double dly = nnd_upwind(m.uy > 0.0, b_m2, b_m1, lm, b_p1, b_p2) * ro(c->inv_dy);
 
         // ---- reverse sweep --------------------------------------------------------
-        double sbar[NV];
-        load_dense(af1, plane, at, sbar);
 #pragma unroll
         for (int i = 0; i < NV; ++i) sbar[i] *= dt;                // adjoint of the source term
         double rb = 0.0, xb = 0.0, yb = 0.0, Tb = 0.0;
@@ -347,29 +352,29 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             for (int r = 2; r < NEE; ++r) {                            // skip m1, m4
                 const double g = -gb.ee[r], d = h.ee[r] - e.ee[r];
                 sg[EE_M[r] - 4][tid] = g * d;
-                hb.ee[r] = R[EE_M[r]] * g;
-                eb.ee[r] = -R[EE_M[r]] * g;
+                hb.ee[r] = ro(R[EE_M[r]]) * g;
+                eb.ee[r] = -ro(R[EE_M[r]]) * g;
             }
 #pragma unroll
             for (int r = 1; r < NOE; ++r) {                            // skip m2
                 const double g = -gb.oe[r], d = h.oe[r] - e.oe[r];
                 sg[OE_M[r] - 4][tid] = g * d;
-                hb.oe[r] = R[OE_M[r]] * g;
-                eb.oe[r] = -R[OE_M[r]] * g;
+                hb.oe[r] = ro(R[OE_M[r]]) * g;
+                eb.oe[r] = -ro(R[OE_M[r]]) * g;
             }
 #pragma unroll
             for (int r = 1; r < NEO; ++r) {                            // skip m3
                 const double g = -gb.eo[r], d = h.eo[r] - e.eo[r];
                 sg[EO_M[r] - 4][tid] = g * d;
-                hb.eo[r] = R[EO_M[r]] * g;
-                eb.eo[r] = -R[EO_M[r]] * g;
+                hb.eo[r] = ro(R[EO_M[r]]) * g;
+                eb.eo[r] = -ro(R[EO_M[r]]) * g;
             }
 #pragma unroll
             for (int r = 0; r < NOO; ++r) {
                 const double g = -gb.oo[r], d = h.oo[r] - e.oo[r];
                 sg[OO_M[r] - 4][tid] = g * d;
-                hb.oo[r] = R[OO_M[r]] * g;
-                eb.oo[r] = -R[OO_M[r]] * g;
+                hb.oo[r] = ro(R[OO_M[r]]) * g;
+                eb.oo[r] = -ro(R[OO_M[r]]) * g;
             }
             A8b = gb.oe[1];          // g_8 = ... - A_8, so A_bar_8 = -g_bar_8 = gb.oe[1]
             A9b = gb.eo[1];
@@ -393,7 +398,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             const double P8 = 4.0 * m.ux * X8 + 2.0 * m.uy * Sg;
             const double P9 = 4.0 * m.uy * X9 + 2.0 * m.ux * Sg;
             const double rT = m.rho * m.T;
-            const double a8c = c->a8c, a9c = c->a9c;
+            const double a8c = ro(c->a8c), a9c = ro(c->a9c);
             rb += m.T * (A8b * a8c * P8 + A9b * a9c * P9);
             Tb += m.rho * (A8b * a8c * P8 + A9b * a9c * P9);
             const double a8cb = A8b * rT * P8, a9cb = A9b * rT * P9;
@@ -405,7 +410,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
             GX = X8b * (1.0 - iDI) - X9b * iDI;                 // adjoint of d u_x / dx
             GY = -X8b * iDI + X9b * (1.0 - iDI);                // adjoint of d u_y / dy
             // a8c = (R_5 - R_8)/R_5, a9c = (R_7 - R_9)/R_7
-            const double R5 = c->R[4], R7 = c->R[6], R8 = c->R[7], R9 = c->R[8];
+            const double R5 = ro(c->R[4]), R7 = ro(c->R[6]), R8 = ro(c->R[7]), R9 = ro(c->R[8]);
             sg[0][tid] += a8cb * R8 / (R5 * R5);
             sg[3][tid] -= a8cb / R5;
             sg[2][tid] += a9cb * R9 / (R7 * R7);
@@ -413,12 +418,12 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
         }
 
         // chemistry: Cochran step and C_i
-        if (c->chem) {
+        if (ro(c->chem)) {
             const double p = m.rho * m.T;
-            const double pm = c->m_is_one ? p : pow(p, c->pm);
-            const double pn = c->n_is_one ? p : pow(p, c->pn);
-            const double ar = c->w1 * pm, br = c->w2 * pn, cc = ar + br;
-            if (m.T > c->Tig && lm < 1.0 && cc > 0.0) {
+            const double pm = ro(c->m_is_one) ? p : pow(p, ro(c->pm));
+            const double pn = ro(c->n_is_one) ? p : pow(p, ro(c->pn));
+            const double ar = ro(c->w1) * pm, br = ro(c->w2) * pn, cc = ar + br;
+            if (m.T > ro(c->Tig) && lm < 1.0 && cc > 0.0) {
                 const double y0 = 1.0 - lm;
                 const double E = exp(cc * dt);
                 const double den = br * y0 + (cc - br * y0) * E;
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                 const double dl = y0 - y1;
                 const double F = dl / dt;
                 const double kk = 1.0 / (I * DI * m.T * m.T);
-                const double K = c->Q * F * kk;
+                const double K = ro(c->Q) * F * kk;
                 // f^eq = M^-1 f_hat^eq (f_hat^eq evaluated again here)
                 double Kb = 0.0, brs = 0.0, bxs = 0.0, bys = 0.0;
                 double* feqb = sbar;          // src_bar is not needed after this loop
@@ -441,8 +446,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
 #pragma unroll
                         for (int d = 0; d < 8; ++d) {
                             const int i = 8 * g + d;
-                            const double cx = c->vg[g] * DUX[d] - m.ux, cy = c->vg[g] * DUY[d] - m.uy;
-                            const double bri = -(1.0 + D) * I * m.T + I * (cx * cx + cy * cy) + c->eta2[g];
+                            const double cx = ro(c->vg[g]) * DUX[d] - m.ux, cy = ro(c->vg[g]) * DUY[d] - m.uy;
+                            const double bri = -(1.0 + D) * I * m.T + I * (cx * cx + cy * cy) + ro(c->eta2[g]);
                             const double sb_i = sbar[i];
                             feqb[i] = sb_i * bri * K;
                             const double brb = sb_i * feq[i] * K;
@@ -456,7 +461,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                 xb += -2.0 * I * bxs;
                 yb += -2.0 * I * bys;
                 sg[20][tid] = Kb * F * kk;                             // d/dQ
-                const double Fb = Kb * c->Q * kk;
+                const double Fb = Kb * ro(c->Q) * kk;
                 Tb += Kb * (-2.0 * K / m.T);
                 {
                     Blocks eb2;
@@ -475,9 +480,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
                 const double abar = ccb;
                 sg[21][tid] = abar * pm;                               // d/domega_1
                 sg[22][tid] = bbar * pn;                               // d/domega_2
-                const double dpm = c->m_is_one ? 1.0 : c->pm * pow(p, c->pm - 1.0);
-                const double dpn = c->n_is_one ? 1.0 : c->pn * pow(p, c->pn - 1.0);
-                const double pb = abar * c->w1 * dpm + bbar * c->w2 * dpn;
+                const double dpm = ro(c->m_is_one) ? 1.0 : ro(c->pm) * pow(p, ro(c->pm) - 1.0);
+                const double dpn = ro(c->n_is_one) ? 1.0 : ro(c->pn) * pow(p, ro(c->pn) - 1.0);
+                const double pb = abar * ro(c->w1) * dpm + bbar * ro(c->w2) * dpn;
                 rb += pb * m.T;
                 Tb += pb * m.rho;
                 lamb -= y0b;
@@ -514,7 +519,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
     }
 }
 
-__global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __restrict__ c,
+__global__ __launch_bounds__(kAdjThreads, 3) void k_adj_stream(const Consts* __restrict__ c,
                                                             const double* __restrict__ f,
                                                             const double* __restrict__ lam,
                                                             const double* __restrict__ af1,
@@ -612,7 +617,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
             }
         }
     };
-    double upd[NV];
+    __shared__ double upd_s[NV][kAdjThreads];   // this thread's 24 updates (own slots only)
     PlaneLoads cur, nxt;
     load_plane(0, cur);
 #pragma unroll
@@ -638,7 +643,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
         }
         const double vx = vg * DUX[d], vy = vg * DUY[d];
         const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + c->eta2[g]) * hb4;
-        upd[i] = a_c - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
+        upd_s[i][threadIdx.x] = a_c - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
         cur = nxt;
     }
 
@@ -657,10 +662,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_stream(const Consts* __rest
     };
     const double lb = lam_t(AX, ox, U + plane, c->inv_dx) + lam_t(AY, oy, U + 2 * plane, c->inv_dy);
     // add the collision part that k_adj_local wrote: 24 loads in one burst, then the stores
+    double o[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) upd[i] = ld(Ob, (uint32_t)i * pb, bc) + upd[i];
+    for (int i = 0; i < NV; ++i) o[i] = ld(Ob, (uint32_t)i * pb, bc);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) st(Ob, (uint32_t)i * pb, bc, upd[i]);
+    for (int i = 0; i < NV; ++i) st(Ob, (uint32_t)i * pb, bc, o[i] + upd_s[i][threadIdx.x]);
     al0[at] += lb;
 }
 

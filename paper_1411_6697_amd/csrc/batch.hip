@@ -114,7 +114,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
     Macro m;
     {
         double gxx = 0.0, gyx = 0.0;
-        if (AMOD && I->amod) {
+        if (AMOD && ro(I->amod)) {
             // the neighbours' velocities, written by the previous step (or k_velocity)
             const uint32_t up = opaque(Ui.plane_bytes);
             gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * k.half_inv_dx;
@@ -125,9 +125,9 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
         Blocks sb, h;
         to_combos(f, sb);
         forward(c->mat, sb, h);
-        m = macro_of(h, c->DI);
+        m = macro_of(h, ro(c->DI));
         double A8 = 0.0, A9 = 0.0;
-        if (AMOD && I->amod) modification(I->a8c, I->a9c, c->DI, m, gxx, 0.0, gyx, 0.0, A8, A9);
+        if (AMOD && ro(I->amod)) modification(ro(I->a8c), ro(I->a9c), ro(c->DI), m, gxx, 0.0, gyx, 0.0, A8, A9);
         lam = ld(L, 0u, oc);
         local_source<CHEM, GEXP>(c, c->mat, lam, A8, A9, m, h, src, dlam, I->R);
     }

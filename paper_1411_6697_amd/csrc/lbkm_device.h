@@ -11,6 +11,16 @@
 
 namespace lbkm {
 
+// A read of constant data (the constants block, per-instance rates) through the constant
+// address space.  Kernels never write these, and such loads stay scalar loads even after
+// stores or fences that the compiler cannot separate from them (LDS stores through a
+// generic pointer, the batch kernel's device-scope fences); through a plain pointer they
+// would turn into vector loads, each a wait that drains all loads in flight.
+template <typename T>
+__device__ __forceinline__ T ro(const T& v) {
+    return *(const __attribute__((address_space(4))) T*)(const void*)&v;
+}
+
 // direction table inside a group
 __device__ constexpr int DUX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int DUY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
@@ -195,7 +205,7 @@ __device__ __forceinline__ void vel_add(VelAcc& a, double vg, int d, double v) {
     if (DUY[d] != 0) a.jy = fma(DUY[d] > 0 ? vg : -vg, v, a.jy);
 }
 __device__ __forceinline__ void vel_add(VelAcc& a, const Consts* __restrict__ c, int g, int d, double v) {
-    vel_add(a, c->vg[g], d, v);
+    vel_add(a, ro(c->vg[g]), d, v);
 }
 
 // minmod: the argument of smaller magnitude if both have the same strict sign, else 0.
@@ -236,19 +246,19 @@ __device__ __forceinline__ double nnd_upwind(bool pos, double fm2, double fm1, d
 // GEXP = false assumes m = n = 1 (the paper's choice), so p^m = p without a pow call.
 template <bool CHEM = true, bool GEXP = true>
 __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double lam, double p, double T) {
-    if (!CHEM || !c->chem) return 0.0;
+    if (!CHEM || !ro(c->chem)) return 0.0;
     double a, b;
     if (GEXP) {
-        a = c->w1 * (c->m_is_one ? p : pow(p, c->pm));
-        b = c->w2 * (c->n_is_one ? p : pow(p, c->pn));
+        a = ro(c->w1) * (ro(c->m_is_one) ? p : pow(p, ro(c->pm)));
+        b = ro(c->w2) * (ro(c->n_is_one) ? p : pow(p, ro(c->pn)));
     } else {
-        a = c->w1 * p;
-        b = c->w2 * p;
+        a = ro(c->w1) * p;
+        b = ro(c->w2) * p;
     }
     const double cc = a + b;
-    if (!(T > c->Tig && lam < 1.0 && cc > 0.0)) return 0.0;
+    if (!(T > ro(c->Tig) && lam < 1.0 && cc > 0.0)) return 0.0;
     const double y0 = 1.0 - lam;
-    const double E = exp(cc * c->dt);
+    const double E = exp(cc * ro(c->dt));
     const double y1 = cc * y0 / (b * y0 + (cc - b * y0) * E);
     return y0 - y1;
 }
@@ -257,19 +267,19 @@ __device__ __forceinline__ double cochran(const Consts* __restrict__ c, double l
 // (Eq. C_i, discrete f^eq), added to src.
 __device__ __forceinline__ void add_chemical(const Consts* __restrict__ c, const Macro& m, double dlam,
                                              const double feq[NV], double src[NV]) {
-    const double F = dlam / c->dt;
-    const double common = c->Q * F / (c->I * c->DI * m.T * m.T);
+    const double F = dlam / ro(c->dt);
+    const double common = ro(c->Q) * F / (ro(c->I) * ro(c->DI) * m.T * m.T);
     // The bracket -(1+D) I T + I |v_i - u|^2 + eta_i^2, already times `common`, split into a
     // part fixed by the group and |v_i| and a part linear in v_i:
     //   common [I (u^2 - (1+D) T) + eta_g^2 + I |v_i|^2] - 2 I common (v_i . u).
-    const double I = c->I;
+    const double I = ro(c->I);
     const double k0 = common * (I * (m.ux * m.ux + m.uy * m.uy) - (1.0 + 2.0) * I * m.T);
     const double px = -2.0 * I * common * m.ux, py = -2.0 * I * common * m.uy;
 #pragma unroll
     for (int g2 = 0; g2 < 3; ++g2) {
-        const double v = c->vg[g2];
-        const double ka = fma(common, c->eta2[g2] + I * (v * v), k0);          // |v_i|^2 = v^2
-        const double kd = fma(common, c->eta2[g2] + I * (2.0 * v * v), k0);    // |v_i|^2 = 2 v^2
+        const double v = ro(c->vg[g2]);
+        const double ka = fma(common, ro(c->eta2[g2]) + I * (v * v), k0);          // |v_i|^2 = v^2
+        const double kd = fma(common, ro(c->eta2[g2]) + I * (2.0 * v * v), k0);    // |v_i|^2 = 2 v^2
         const double qx = v * px, qy = v * py, sp = qx + qy, sm = qx - qy;
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
@@ -297,17 +307,17 @@ __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const
     const double* __restrict__ R = Rk ? Rk : c->R;     // R_1..R_24 (per instance when batched)
     {
         Blocks e;
-        equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+        equilibrium(m.rho, m.ux, m.uy, m.T, ro(c->I), e);
         // g = R (f_hat - f_hat^eq) - A_hat, Delta_1..4 = 0
         Blocks g;
 #pragma unroll
-        for (int r = 0; r < NEE; ++r) g.ee[r] = R[EE_M[r]] * (h.ee[r] - e.ee[r]);
+        for (int r = 0; r < NEE; ++r) g.ee[r] = ro(R[EE_M[r]]) * (h.ee[r] - e.ee[r]);
 #pragma unroll
-        for (int r = 0; r < NOE; ++r) g.oe[r] = R[OE_M[r]] * (h.oe[r] - e.oe[r]);
+        for (int r = 0; r < NOE; ++r) g.oe[r] = ro(R[OE_M[r]]) * (h.oe[r] - e.oe[r]);
 #pragma unroll
-        for (int r = 0; r < NEO; ++r) g.eo[r] = R[EO_M[r]] * (h.eo[r] - e.eo[r]);
+        for (int r = 0; r < NEO; ++r) g.eo[r] = ro(R[EO_M[r]]) * (h.eo[r] - e.eo[r]);
 #pragma unroll
-        for (int r = 0; r < NOO; ++r) g.oo[r] = R[OO_M[r]] * (h.oo[r] - e.oo[r]);
+        for (int r = 0; r < NOO; ++r) g.oo[r] = ro(R[OO_M[r]]) * (h.oo[r] - e.oo[r]);
         g.ee[0] = 0.0;   // m1
         g.ee[1] = 0.0;   // m4
         g.oe[0] = 0.0;   // m2
@@ -329,7 +339,7 @@ __device__ __forceinline__ void local_source(const Consts* __restrict__ c, const
         double T2 = m.T;
         asm volatile("" : "+v"(T2));
         Blocks e2;
-        equilibrium(m.rho, m.ux, m.uy, T2, c->I, e2);
+        equilibrium(m.rho, m.ux, m.uy, T2, ro(c->I), e2);
         Blocks se;
         inverse(M, e2, se);
         double feq[NV];
@@ -344,21 +354,21 @@ __device__ __forceinline__ Macro macro_sums(const Consts* __restrict__ c, const 
     double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-        const double v = c->vg[g];
+        const double v = ro(c->vg[g]);
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             const double x = f[8 * g + d];
             r += x;
             if (DUX[d] != 0) jx = fma(DUX[d] > 0 ? v : -v, x, jx);
             if (DUY[d] != 0) jy = fma(DUY[d] > 0 ? v : -v, x, jy);
-            e = fma((double)(DUX[d] * DUX[d] + DUY[d] * DUY[d]) * (v * v) + c->eta2[g], x, e);
+            e = fma((double)(DUX[d] * DUX[d] + DUY[d] * DUY[d]) * (v * v) + ro(c->eta2[g]), x, e);
         }
     }
     Macro m;
     m.rho = r;
     m.ux = jx / r;
     m.uy = jy / r;
-    m.T = (e / r - m.ux * m.ux - m.uy * m.uy) / c->DI;
+    m.T = (e / r - m.ux * m.ux - m.uy * m.uy) / ro(c->DI);
     return m;
 }
 
@@ -369,12 +379,12 @@ __device__ __forceinline__ void srt_source(const Consts* __restrict__ c, const M
                                            const Macro& m, const double f[NV], double src[NV],
                                            double& dlam) {
     Blocks e, se;
-    equilibrium(m.rho, m.ux, m.uy, m.T, c->I, e);
+    equilibrium(m.rho, m.ux, m.uy, m.T, ro(c->I), e);
     inverse(M, e, se);
     double feq[NV];
     from_combos(se, feq);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) src[i] = (feq[i] - f[i]) * c->inv_tau;
+    for (int i = 0; i < NV; ++i) src[i] = (feq[i] - f[i]) * ro(c->inv_tau);
     dlam = cochran<CHEM, GEXP>(c, lam, m.rho * m.T, m.T);
     if (CHEM && dlam != 0.0) add_chemical(c, m, dlam, feq, src);
 }
@@ -393,7 +403,7 @@ __device__ __forceinline__ void modification(double a8c, double a9c, double DI, 
 __device__ __forceinline__ void modification(const Consts* __restrict__ c, const Macro& m,
                                              double dux_dx, double dux_dy, double duy_dx,
                                              double duy_dy, double& A8, double& A9) {
-    modification(c->a8c, c->a9c, c->DI, m, dux_dx, dux_dy, duy_dx, duy_dy, A8, A9);
+    modification(ro(c->a8c), ro(c->a9c), ro(c->DI), m, dux_dx, dux_dy, duy_dx, duy_dy, A8, A9);
 }
 
 // A structure-of-arrays buffer seen through one buffer resource: plane i of a cell is at

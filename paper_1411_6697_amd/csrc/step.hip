@@ -42,19 +42,19 @@ struct Off {
 };
 
 __device__ __forceinline__ Off stencil_offsets(const Consts* __restrict__ c, int x, int y) {
-    const int nx = c->nx, ny = c->ny;
-    const uint32_t p = (uint32_t)c->pitch;
+    const int nx = ro(c->nx), ny = ro(c->ny);
+    const uint32_t p = (uint32_t)ro(c->pitch);
     const uint32_t row = (uint32_t)y * p;
     Off s;
     s.c = (row + x) * 8u;
-    s.xm2 = (row + wrap(x - 2, nx, c->bc_x)) * 8u;
-    s.xm1 = (row + wrap(x - 1, nx, c->bc_x)) * 8u;
-    s.xp1 = (row + wrap(x + 1, nx, c->bc_x)) * 8u;
-    s.xp2 = (row + wrap(x + 2, nx, c->bc_x)) * 8u;
-    s.ym2 = ((uint32_t)wrap(y - 2, ny, c->bc_y) * p + x) * 8u;
-    s.ym1 = ((uint32_t)wrap(y - 1, ny, c->bc_y) * p + x) * 8u;
-    s.yp1 = ((uint32_t)wrap(y + 1, ny, c->bc_y) * p + x) * 8u;
-    s.yp2 = ((uint32_t)wrap(y + 2, ny, c->bc_y) * p + x) * 8u;
+    s.xm2 = (row + wrap(x - 2, nx, ro(c->bc_x))) * 8u;
+    s.xm1 = (row + wrap(x - 1, nx, ro(c->bc_x))) * 8u;
+    s.xp1 = (row + wrap(x + 1, nx, ro(c->bc_x))) * 8u;
+    s.xp2 = (row + wrap(x + 2, nx, ro(c->bc_x))) * 8u;
+    s.ym2 = ((uint32_t)wrap(y - 2, ny, ro(c->bc_y)) * p + x) * 8u;
+    s.ym1 = ((uint32_t)wrap(y - 1, ny, ro(c->bc_y)) * p + x) * 8u;
+    s.yp1 = ((uint32_t)wrap(y + 1, ny, ro(c->bc_y)) * p + x) * 8u;
+    s.yp2 = ((uint32_t)wrap(y + 2, ny, ro(c->bc_y)) * p + x) * 8u;
     return s;
 }
 
@@ -69,27 +69,27 @@ struct Ghosts {
 __device__ __forceinline__ Ghosts ghosts_of(const Consts* __restrict__ c, int x, int y) {
     Ghosts g;
     g.is = 0;
-    const uint32_t L = (uint32_t)c->gL;
+    const uint32_t L = (uint32_t)ro(c->gL);
     auto set = [&](int k, int side, int layer, int along) {
         g.is |= 1u << k;
         g.off[k] = ((uint32_t)(side * 2 + layer) * L + (uint32_t)along) * 8u;
     };
 #pragma unroll
     for (int k = 0; k < 8; ++k) g.off[k] = 0u;
-    const int nx = c->nx, ny = c->ny;
-    if (c->wall[0] != kWallNone) {
+    const int nx = ro(c->nx), ny = ro(c->ny);
+    if (ro(c->wall[0]) != kWallNone) {
         if (x < 2) set(0, 0, 1 - x, y);
         if (x < 1) set(1, 0, 0, y);
     }
-    if (c->wall[1] != kWallNone) {
+    if (ro(c->wall[1]) != kWallNone) {
         if (x + 1 >= nx) set(2, 1, x + 1 - nx, y);
         if (x + 2 >= nx) set(3, 1, x + 2 - nx, y);
     }
-    if (c->wall[2] != kWallNone) {
+    if (ro(c->wall[2]) != kWallNone) {
         if (y < 2) set(4, 2, 1 - y, x);
         if (y < 1) set(5, 2, 0, x);
     }
-    if (c->wall[3] != kWallNone) {
+    if (ro(c->wall[3]) != kWallNone) {
         if (y + 1 >= ny) set(6, 3, y + 1 - ny, x);
         if (y + 2 >= ny) set(7, 3, y + 2 - ny, x);
     }
@@ -128,10 +128,10 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
         // velocities of the ghost points come from the ghost buffer's velocity planes
         const uint32_t up = opaque(Ui.plane_bytes), gp = opaque(Gb->plane_bytes);
         const uint32_t gx0 = (NV + 1) * gp, gy0 = (NV + 2) * gp;
-        gxx = (sld<true>(Ui, 0u, s.xp1, *Gb, gx0, *gh, 2) - sld<true>(Ui, 0u, s.xm1, *Gb, gx0, *gh, 1)) * c->half_inv_dx;
-        gyx = (sld<true>(Ui, up, s.xp1, *Gb, gy0, *gh, 2) - sld<true>(Ui, up, s.xm1, *Gb, gy0, *gh, 1)) * c->half_inv_dx;
-        gxy = (sld<true>(Ui, 0u, s.yp1, *Gb, gx0, *gh, 6) - sld<true>(Ui, 0u, s.ym1, *Gb, gx0, *gh, 5)) * c->half_inv_dy;
-        gyy = (sld<true>(Ui, up, s.yp1, *Gb, gy0, *gh, 6) - sld<true>(Ui, up, s.ym1, *Gb, gy0, *gh, 5)) * c->half_inv_dy;
+        gxx = (sld<true>(Ui, 0u, s.xp1, *Gb, gx0, *gh, 2) - sld<true>(Ui, 0u, s.xm1, *Gb, gx0, *gh, 1)) * ro(c->half_inv_dx);
+        gyx = (sld<true>(Ui, up, s.xp1, *Gb, gy0, *gh, 2) - sld<true>(Ui, up, s.xm1, *Gb, gy0, *gh, 1)) * ro(c->half_inv_dx);
+        gxy = (sld<true>(Ui, 0u, s.yp1, *Gb, gx0, *gh, 6) - sld<true>(Ui, 0u, s.ym1, *Gb, gx0, *gh, 5)) * ro(c->half_inv_dy);
+        gyy = (sld<true>(Ui, up, s.yp1, *Gb, gy0, *gh, 6) - sld<true>(Ui, up, s.ym1, *Gb, gy0, *gh, 5)) * ro(c->half_inv_dy);
     } else if (AMOD) {
         // the four neighbours' velocities join the raised-priority window of the centre loads
         const uint32_t up = opaque(Ui.plane_bytes);
@@ -143,16 +143,16 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
         lam = ld(L, 0u, s.c);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_setprio(0);
-        gxx = (a0 - a1) * c->half_inv_dx;   // d u_x / dx
-        gyx = (a2 - a3) * c->half_inv_dx;   // d u_y / dx
-        gxy = (b0 - b1) * c->half_inv_dy;   // d u_x / dy
-        gyy = (b2 - b3) * c->half_inv_dy;   // d u_y / dy
+        gxx = (a0 - a1) * ro(c->half_inv_dx);   // d u_x / dx
+        gyx = (a2 - a3) * ro(c->half_inv_dx);   // d u_y / dx
+        gxy = (b0 - b1) * ro(c->half_inv_dy);   // d u_x / dy
+        gyy = (b2 - b3) * ro(c->half_inv_dy);   // d u_y / dy
     }
     if constexpr (!AMOD || GHOST) load_cell_first(F, s.c, f, &L, &lam);
     Blocks sb, h;
     to_combos(f, sb);
     forward(M, sb, h);
-    m = macro_of(h, c->DI);
+    m = macro_of(h, ro(c->DI));
     double A8 = 0.0, A9 = 0.0;
     if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
     local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
@@ -177,17 +177,17 @@ __device__ __forceinline__ void cell_source_held(const Consts* __restrict__ c, c
         const double a0 = ld(Ui, 0u, s.xp1), a1 = ld(Ui, 0u, s.xm1), a2 = ld(Ui, up, s.xp1), a3 = ld(Ui, up, s.xm1);
         const double b0 = ld(Ui, 0u, s.yp1), b1 = ld(Ui, 0u, s.ym1), b2 = ld(Ui, up, s.yp1), b3 = ld(Ui, up, s.ym1);
         lam = ld(L, 0u, s.c);
-        gxx = (a0 - a1) * c->half_inv_dx;   // d u_x / dx
-        gyx = (a2 - a3) * c->half_inv_dx;   // d u_y / dx
-        gxy = (b0 - b1) * c->half_inv_dy;   // d u_x / dy
-        gyy = (b2 - b3) * c->half_inv_dy;   // d u_y / dy
+        gxx = (a0 - a1) * ro(c->half_inv_dx);   // d u_x / dx
+        gyx = (a2 - a3) * ro(c->half_inv_dx);   // d u_y / dx
+        gxy = (b0 - b1) * ro(c->half_inv_dy);   // d u_x / dy
+        gyy = (b2 - b3) * ro(c->half_inv_dy);   // d u_y / dy
     } else {
         lam = ld(L, 0u, s.c);
     }
     Blocks sb, h;
     to_combos(f, sb);
     forward(M, sb, h);
-    m = macro_of(h, c->DI);
+    m = macro_of(h, ro(c->DI));
     double A8 = 0.0, A9 = 0.0;
     if (AMOD) modification(c, m, gxx, gxy, gyx, gyy, A8, A9);
     local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
@@ -203,15 +203,15 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
                                           const double* __restrict__ lin, double* __restrict__ lout,
                                           const double* __restrict__ uin, double* __restrict__ uout,
                                           const Blend& bl, const double* __restrict__ gb) {
-    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
+    const Soa F = soa(fin, ro(c->plane)), G = soa(fout, ro(c->plane));
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
-    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
+    const Soa Ui = soa(uin, ro(c->plane)), Uo = soa(uout, ro(c->plane));
     // f^n, lambda^n of a Runge-Kutta stage; null: the output buffers themselves (in place)
-    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, ro(c->plane));
     const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
     const Off s = stencil_offsets(c, x, y);
     // wall sides: the ghost buffer and which stencil points read it
-    const Soa Gb = soa(GHOST ? gb : fin, 8 * (int64_t)c->gL);
+    const Soa Gb = soa(GHOST ? gb : fin, 8 * (int64_t)ro(c->gL));
     Ghosts gh;
     if (GHOST) gh = ghosts_of(c, x, y);
 
@@ -224,14 +224,14 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
     // Phase 2: NND streaming plane by plane; the centre value is read again (a cache hit)
     // so that only src[] stays live across the planes.  GH: stencil points may lie on wall
     // ghost layers (instantiated only in the wall specialisation).
-    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+    const double dt = ro(c->dt), idx_ = ro(c->inv_dx), idy = ro(c->inv_dy);
     const uint32_t pb = opaque(F.plane_bytes);
     auto phase2 = [&](auto gh_on) {
         constexpr bool GH = decltype(gh_on)::value;
         VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const double v = c->vg[g];
+            const double v = ro(c->vg[g]);
             const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
@@ -296,11 +296,11 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly = tid / TX;
     const int x = x0 + lx, y = y0 + ly;
-    const bool inside = x < c->nx && y < c->ny;
-    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
+    const bool inside = x < ro(c->nx) && y < ro(c->ny);
+    const Soa F = soa(fin, ro(c->plane)), G = soa(fout, ro(c->plane));
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
-    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
-    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
+    const Soa Ui = soa(uin, ro(c->plane)), Uo = soa(uout, ro(c->plane));
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, ro(c->plane));
     const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
 
     // the patch values this thread loads: LDS index and within-plane byte offset
@@ -309,9 +309,9 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     for (int j = 0; j < P::NS; ++j) {
         const int k = tid + j * P::NT;
         const int px = k % P::PW, py = k / P::PW;
-        const int gx = wrap(x0 - 2 + px, c->nx, c->bc_x);
-        const int gy = wrap(y0 - 2 + py, c->ny, c->bc_y);
-        goff[j] = ((uint32_t)gy * (uint32_t)c->pitch + (uint32_t)gx) * 8u;
+        const int gx = wrap(x0 - 2 + px, ro(c->nx), ro(c->bc_x));
+        const int gy = wrap(y0 - 2 + py, ro(c->ny), ro(c->bc_y));
+        goff[j] = ((uint32_t)gy * (uint32_t)ro(c->pitch) + (uint32_t)gx) * 8u;
     }
 
     // Phase 1: collision and chemistry of this thread's cell
@@ -327,9 +327,9 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase 2: planes 0..23 of f, then lambda (plane 24), through the LDS patch
-    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+    const double dt = ro(c->dt), idx_ = ro(c->inv_dx), idy = ro(c->inv_dy);
     const uint32_t pb = opaque(F.plane_bytes);
-    const uint32_t out_off = ((uint32_t)y * (uint32_t)c->pitch + (uint32_t)x) * 8u;
+    const uint32_t out_off = ((uint32_t)y * (uint32_t)ro(c->pitch) + (uint32_t)x) * 8u;
     const int cidx = (ly + 2) * P::PW + (lx + 2);
     double pre[P::NS];
     VelAcc va;                                  // velocity of the new state (for A_hat)
@@ -353,7 +353,7 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
         const double f0 = q[0];
         if (i < NV) {
             const int g = i / 8, d = i % 8;
-            const double v = c->vg[g];
+            const double v = ro(c->vg[g]);
             const double wx = dt * v * idx_, wy = dt * v * idy;
             double a = f0;
             if (DUX[d] > 0) a = fma(-wx, nnd_pos(q[-2], q[-1], f0, q[1]), a);
@@ -422,14 +422,14 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
     const int tid = (int)threadIdx.x;
     const int x = tx * TX + tid % TX;
     const int y = ty * TY + tid / TX;
-    if (x >= c->nx || y >= c->ny) return;
-    const Soa F = soa(fin, c->plane), G = soa(fout, c->plane);
+    if (x >= ro(c->nx) || y >= ro(c->ny)) return;
+    const Soa F = soa(fin, ro(c->plane)), G = soa(fout, ro(c->plane));
     const Soa L = soa(lin, 0), Lo = soa(lout, 0);
-    const Soa Ui = soa(uin, c->plane), Uo = soa(uout, c->plane);
-    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, c->plane);
+    const Soa Ui = soa(uin, ro(c->plane)), Uo = soa(uout, ro(c->plane));
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, ro(c->plane));
     const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
     const Off s = stencil_offsets(c, x, y);
-    const double dt = c->dt, idx_ = c->inv_dx, idy = c->inv_dy;
+    const double dt = ro(c->dt), idx_ = ro(c->inv_dx), idy = ro(c->inv_dy);
 
     // Phase A: the 24 centre values in one burst at raised wave priority (all of them miss
     // in the caches: many loads in flight per wave), then the NND streaming of every plane,
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
         const uint32_t pb = opaque(F.plane_bytes);
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const double v = c->vg[g];
+            const double v = ro(c->vg[g]);
             const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3)
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;
     const int x = tx * TX + (int)(threadIdx.x % TX);
     const int y = ty * TY + (int)(threadIdx.x / TX);
-    if (x >= c->nx || y >= c->ny) return;
+    if (x >= ro(c->nx) || y >= ro(c->ny)) return;
     step_cell<AMOD, CHEM, GEXP, SRT, BLEND, GHOST>(c, c->mat, x, y, fin, fout, lin, lout, uin, uout, bl, gb);
 }
 
