@@ -46,30 +46,42 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tile=None):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and (when `tile` = (tile_x,
-    tile_y, lds) is given) on the same launch shape; else None."""
+STEP_KERNELS = {0: "k_step", 1: "k_step_lds", 2: "k_step_sf"}    # launch mode -> kernel
+
+
+def step_kernel_name(tile) -> str:
+    """Name of the step kernel a launch (tile_x, tile_y, mode) runs, as the profiler shows
+    it up to the specialisation flags."""
+    return f"{STEP_KERNELS[int(tile[2])]}<{int(tile[0])},{int(tile[1])}>"
+
+
+def measured_traffic(tile):
+    """HBM bytes per launch of the step kernel at launch `tile` = (tile_x, tile_y, mode),
+    from the committed rocprofv3 counter summary, if that was taken on the current kernel
+    source and holds that launch shape; else None."""
     if not os.path.exists(PMC_FILE):
         return None
-    vals = {}
+    src_hash, per_kernel = None, {}
     with open(PMC_FILE) as fh:
         for line in fh:
             parts = line.split()
-            if len(parts) >= 2 and not line.startswith("#"):
-                vals[parts[0]] = parts[1]
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+            if not parts or line.startswith("#"):
+                continue
+            if parts[0] == "kernel_source_sha256" and len(parts) > 1:
+                src_hash = parts[1]
+            elif parts[0] == "kernel" and len(parts) > 2:
+                kv = dict(zip(parts[2::2], parts[3::2]))
+                per_kernel[parts[1]] = kv
+    if src_hash != kernel_source_hash():
         return None
-    if tile is not None:
-        import re
-        m = re.match(r"k_step(_lds|_sf)?<(\d+),(\d+),", vals.get("kernel", ""))
-        mode = {None: 0, "_lds": 1, "_sf": 2}[m.group(1)] if m else -1
-        if not m or (int(m.group(2)), int(m.group(3)), mode) != tuple(int(v) for v in tile):
-            return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    want = STEP_KERNELS[int(tile[2])] + f"<{int(tile[0])},{int(tile[1])},"
+    for name, kv in per_kernel.items():
+        if name.startswith(want):
+            try:
+                return float(kv["hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def time_steps(sim, steps, warmup):
@@ -473,7 +485,7 @@ def main():
                    "state_finite_after_run": bool(ok)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step",
+                     "traffic": traffic, "kernel": step_kernel_name(launch[:3]),
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL,
                      "copy_kernel_gbs": round(ceiling, 1)},
         "inert_Q0": inert,
