@@ -398,6 +398,41 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
     return true;
 }
 
+// Lane moves of a double across the wave (DPP): lane i receives lane i-1's value
+// (from_left) or lane i+1's (from_right); the end lane keeps 0 and is patched by the caller.
+__device__ __forceinline__ double from_left(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);   // wave_shr:1
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);   // wave_shl:1
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The x-neighbours of one plane for a wave that holds 64 consecutive cells of a row, from
+// the centre values of the neighbouring lanes.  h is the plane's halo: lanes 0-31 hold the
+// value at x0-1 (lane 0: x0-2), lanes 32-63 the value at x0+64 (lane 63: x0+65), x0 being
+// the wave's first cell, each index under the boundary rule.
+struct XNeighbours {
+    double m2, m1, p1, p2;
+};
+__device__ __forceinline__ XNeighbours x_neighbours(double f0, double h, int lane) {
+    const double l1 = from_left(f0), r1 = from_right(f0);
+    const double l2 = from_left(l1), r2 = from_right(r1);
+    // every lane takes part in the halo load (left to itself the compiler would load it on
+    // the end lanes only, behind a branch and a wait per plane)
+    asm("" : "+v"(h));
+    const double hl = from_right(h), hr = from_left(h);
+    XNeighbours n;
+    n.m2 = lane < 2 ? h : l2;
+    n.m1 = lane == 0 ? hl : l1;     // lane 0: x0-1, held by lane 1
+    n.p1 = lane == 63 ? hr : r1;    // lane 63: x0+64, held by lane 62
+    n.p2 = lane >= 62 ? h : r2;
+    return n;
+}
+
 // Stream-first step: every value of the input state is read from HBM once.  Phase A walks
 // the 24 planes, reading each plane's centre value with its NND stencil, and keeps the
 // streamed value f_i - dt v_i . grad_NND f_i in this thread's slots of LDS and the 24
@@ -436,7 +471,21 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
     // whose stencil neighbours are mostly the lines those bursts have just brought in.
     double f[NV];
     load_cell_first(F, s.c, f);
-    {
+    // The x-neighbours of a cell are the centre values of the neighbouring lanes when the
+    // wave holds 64 consecutive cells of a row (tiles 64 or more wide, away from a ragged
+    // right edge): lane moves then replace two of the three x-stencil loads of a plane, and
+    // one halo load per plane serves the lanes at both ends.  L1 bandwidth, not HBM, bounds
+    // this phase (about 140 eight-byte gathers per cell), so the loads saved are what counts.
+    const int lane = tid & 63;
+    const bool lanes_form_row = TX % 64 == 0 && (x - lane) + 64 <= ro(c->nx);   // uniform per wave
+    uint32_t halo = 0u;
+    if (TX % 64 == 0) {
+        const int x0 = x - lane, nx = ro(c->nx), bcx = ro(c->bc_x);
+        const int hx = lane < 32 ? (lane == 0 ? x0 - 2 : x0 - 1) : (lane == 63 ? x0 + 65 : x0 + 64);
+        halo = ((uint32_t)y * (uint32_t)ro(c->pitch) + (uint32_t)wrap(hx, nx, bcx)) * 8u;
+    }
+    auto phase_a = [&](auto by_lanes) {
+        constexpr bool XL = decltype(by_lanes)::value;
         const uint32_t pb = opaque(F.plane_bytes);
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
@@ -447,13 +496,27 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
                 const uint32_t so = (uint32_t)(8 * g + d) * pb;
                 const double f0 = f[8 * g + d];
                 double a = f0;
-                if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)), a);
-                if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)), a);
+                if (XL && DUX[d] != 0) {
+                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo), lane);
+                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
+                    if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
+                } else {
+                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)), a);
+                    if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)), a);
+                }
                 if (DUY[d] > 0) a = fma(-wy, nnd_pos(ld(F, so, s.ym2), ld(F, so, s.ym1), f0, ld(F, so, s.yp1)), a);
                 if (DUY[d] < 0) a = fma(wy, nnd_neg(ld(F, so, s.ym1), f0, ld(F, so, s.yp1), ld(F, so, s.yp2)), a);
                 streamed[(8 * g + d) * NT + tid] = a;
             }
         }
+    };
+    if constexpr (TX % 64 == 0) {
+        if (lanes_form_row)
+            phase_a(std::true_type{});
+        else
+            phase_a(std::false_type{});
+    } else {
+        phase_a(std::false_type{});
     }
     __builtin_amdgcn_sched_barrier(0);
 

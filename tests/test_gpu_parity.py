@@ -299,12 +299,18 @@ VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 
                                W.kh(n=2048, steps=20).with_(nx=2040, ny=9),
                                W.kh(n=2048, steps=30).with_(nx=130, ny=67, tau=1.0 / 2e4),
                                W.detonation(nx=333, ny=7, steps=12).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
-                                                                         bc_y="outflow", rk=3)],
-                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67", "det-amod-rk3-333x7"])
+                                                                         bc_y="outflow", rk=3),
+                               W.kh(n=2048, steps=20).with_(nx=64, ny=5),
+                               W.detonation(nx=128, ny=2, steps=20).with_(R=W.rates(100.0, r8=200.0, r9=150.0))],
+                         ids=["det-amod-333x7", "kh-130x67", "kh-2040x9", "kh-srt-130x67", "det-amod-rk3-333x7",
+                              "kh-64x5", "det-amod-128x2"])
 def test_launch_variants_give_bitwise_identical_results(w):
     """Every compiled launch shape (collide-first with direct or LDS-staged stencil loads, and
     stream-first) in both tile orders computes the same bits; the grids do not divide into tiles and use both boundary rules (2040 wide: the
-    column-band order is taken, with a ragged last tile column)."""
+    column-band order is taken, with a ragged last tile column).  The stream-first shapes 64 or
+    more cells wide take x-neighbours from neighbouring lanes where a wave holds 64 cells of
+    a row and load them elsewhere; the 64- and 128-wide grids have only such waves, whose
+    halo wraps or clamps at both ends of the row."""
     F = {k: np.ascontiguousarray(v[:w.ny, :w.nx]) for k, v in (w.fields() if w.ny * w.nx < 1e5 else
                                                                   W.kh(n=2048).fields()).items()}
     ref = None
