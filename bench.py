@@ -16,7 +16,7 @@ beside them.  Prints one JSON line.
   python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu-baseline]
                   [--no-inert] [--no-batched] [--no-adjoint] [--no-srt] [--no-rk] [--no-walls]
                   [--no-small]
-                  [--launch TXxTY[l|s]:ORDER]   (fix the step's launch instead of autotuning it)
+                  [--launch TXxTY[l|s|h]:ORDER]   (fix the step's launch instead of autotuning it)
 """
 
 from __future__ import annotations
@@ -46,7 +46,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-STEP_KERNELS = {0: "k_step", 1: "k_step_lds", 2: "k_step_sf"}    # launch mode -> kernel
+STEP_KERNELS = {0: "k_step", 1: "k_step_lds", 2: "k_step_sf", 3: "k_step_sh"}    # launch mode -> kernel
 
 
 def step_kernel_name(tile) -> str:
@@ -378,8 +378,9 @@ def main():
     ap.add_argument("--no-walls", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--launch", default=None,
-                    help="fix the KH step's launch instead of autotuning it: TXxTY[l|s]:ORDER, e.g. 64x4s:1 "
-                         "(l = LDS-staged stencil, s = stream-first kernel, ORDER 1 = column bands); used to "
+                    help="fix the KH step's launch instead of autotuning it: TXxTY[l|s|h]:ORDER, e.g. 64x4s:1 "
+                         "(l = LDS-staged stencil, s = stream-first kernel, h = centre values shared in LDS, ORDER 1 = "
+                         "column bands); used to "
                          "profile a stated shape")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -397,8 +398,8 @@ def main():
     sim = lbkm.sim_from_workload(w)
     if args.launch:
         shape, order = args.launch.split(":")
-        lds = 1 if shape.endswith("l") else (2 if shape.endswith("s") else 0)
-        tx, ty = (int(v) for v in shape.rstrip("ls").split("x"))
+        lds = {"l": 1, "s": 2, "h": 3}.get(shape[-1], 0)
+        tx, ty = (int(v) for v in shape.rstrip("lsh").split("x"))
         sim.set_tile(tx, ty, lds)
         sim.set_tile_order(int(order))
         launch = (tx, ty, lds, int(order))

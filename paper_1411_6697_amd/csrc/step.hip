@@ -553,6 +553,143 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
     st_stream(Lo, 0u, s.c, lnew);
 }
 
+// Collide first with the tile's centre values shared in LDS.  Each wave loads its cells'
+// 24 centre values in one burst and writes them to LDS; after the collision and one
+// barrier, the streaming phase takes the cell's own value and its y-neighbours inside the
+// tile from LDS, its x-neighbours from the neighbouring lanes (a wave is 64 cells of one
+// row), and loads only the halo: the rows beyond the tile and the two cells beyond each
+// end of the row.  The choice between LDS and memory is fixed at compile time per row of
+// the tile, so the loads of consecutive planes stay free to overlap; rows within two cells
+// of a y edge (where the boundary rule may map a neighbour anywhere) and waves that are not
+// whole rows load every neighbour.
+template <int RW>
+struct RowOf {
+    static constexpr int value = RW;
+};
+
+template <bool IN>
+__device__ __forceinline__ double centre_or_load(const double* slot, int delta, const Soa& F, uint32_t so,
+                                                 uint32_t off) {
+    if constexpr (IN)
+        return slot[delta];
+    else
+        return ld(F, so, off);
+}
+
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
+__global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts* __restrict__ c,
+                                                               const double* __restrict__ fin,
+                                                               double* __restrict__ fout,
+                                                               const double* __restrict__ lin,
+                                                               double* __restrict__ lout,
+                                                               const double* __restrict__ uin,
+                                                               double* __restrict__ uout, int gx, int ntiles,
+                                                               int vertical, Blend bl) {
+    static_assert(TX % 64 == 0, "a wave must hold cells of one row");
+    constexpr int NT = TX * TY;
+    __shared__ double cen[NV * NT];
+    int tx, ty;
+    if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;   // uniform over the work-group
+    const int tid = (int)threadIdx.x;
+    const int x = tx * TX + tid % TX;
+    const int y = ty * TY + tid / TX;
+    const int nx = ro(c->nx), ny = ro(c->ny);
+    const bool inside = x < nx && y < ny;     // every thread stays for the barrier
+    const Soa F = soa(fin, ro(c->plane)), G = soa(fout, ro(c->plane));
+    const Soa L = soa(lin, 0), Lo = soa(lout, 0);
+    const Soa Ui = soa(uin, ro(c->plane)), Uo = soa(uout, ro(c->plane));
+    const Soa Fn = soa(BLEND ? (bl.fn ? bl.fn : fout) : fin, ro(c->plane));
+    const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
+    const Off s = stencil_offsets(c, inside ? x : 0, inside ? y : 0);
+    const double dt = ro(c->dt), idx_ = ro(c->inv_dx), idy = ro(c->inv_dy);
+
+    // Phase 1: centre burst, the values to LDS, collision and chemistry
+    double src[NV], dlam = 0.0, lam = 0.0;
+    Macro m{1.0, 0.0, 0.0, 1.0};
+    if (inside) {
+        double f[NV];
+        load_cell_first(F, s.c, f);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cen[i * NT + tid] = f[i];
+        cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, L, Ui, s, src, dlam, lam, m);
+    }
+    __syncthreads();
+    if (!inside) return;
+
+    // Phase 2: NND streaming from LDS and the halo, forward Euler, store
+    const int lane = tid & 63;
+    const bool lanes_form_row = (x - lane) + 64 <= nx;                  // uniform per wave
+    uint32_t halo;
+    {
+        const int x0 = x - lane;
+        const int hx = lane < 32 ? (lane == 0 ? x0 - 2 : x0 - 1) : (lane == 63 ? x0 + 65 : x0 + 64);
+        halo = ((uint32_t)y * (uint32_t)ro(c->pitch) + (uint32_t)wrap(hx, nx, ro(c->bc_x))) * 8u;
+    }
+    auto phase2 = [&](auto by_lanes, auto row) {
+        constexpr bool XL = decltype(by_lanes)::value;
+        constexpr int RW = decltype(row)::value;   // row of the tile, -1: load every y-neighbour
+        constexpr bool IM2 = RW >= 2, IM1 = RW >= 1, IP1 = RW >= 0 && RW + 1 < TY, IP2 = RW >= 0 && RW + 2 < TY;
+        const uint32_t pb = opaque(F.plane_bytes);
+        VelAcc va;                                  // velocity of the new state (for A_hat)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const double v = ro(c->vg[g]);
+            const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                const int i = 8 * g + d;
+                const uint32_t so = (uint32_t)i * pb;
+                const double* slot = cen + i * NT + tid;
+                const double f0 = slot[0];
+                double a = f0;
+                if (XL && DUX[d] != 0) {
+                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo), lane);
+                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
+                    if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
+                } else {
+                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)), a);
+                    if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)), a);
+                }
+                if (DUY[d] > 0)
+                    a = fma(-wy, nnd_pos(centre_or_load<IM2>(slot, -2 * TX, F, so, s.ym2),
+                                         centre_or_load<IM1>(slot, -TX, F, so, s.ym1), f0,
+                                         centre_or_load<IP1>(slot, TX, F, so, s.yp1)), a);
+                if (DUY[d] < 0)
+                    a = fma(wy, nnd_neg(centre_or_load<IM1>(slot, -TX, F, so, s.ym1), f0,
+                                        centre_or_load<IP1>(slot, TX, F, so, s.yp1),
+                                        centre_or_load<IP2>(slot, 2 * TX, F, so, s.yp2)), a);
+                double out = fma(dt, src[i], a);
+                if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
+                if (AMOD) vel_add(va, c, g, d, out);
+                st_stream(G, so, s.c, out);
+            }
+        }
+        if (AMOD) {
+            st_stream(Uo, 0u, s.c, va.jx / va.r);
+            st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
+        }
+    };
+    const int rw = __builtin_amdgcn_readfirstlane(tid / TX);
+    if (lanes_form_row && y >= 2 && y + 2 < ny) {
+        static_assert(TY <= 4, "rows of the tile are specialised up to four");
+        if (rw == 0) phase2(std::true_type{}, RowOf<0>{});
+        else if (TY > 1 && rw == 1) phase2(std::true_type{}, RowOf<(TY > 1 ? 1 : 0)>{});
+        else if (TY > 2 && rw == 2) phase2(std::true_type{}, RowOf<(TY > 2 ? 2 : 0)>{});
+        else if (TY > 3) phase2(std::true_type{}, RowOf<(TY > 3 ? 3 : 0)>{});
+    } else if (lanes_form_row) {
+        phase2(std::true_type{}, RowOf<-1>{});
+    } else {
+        phase2(std::false_type{}, RowOf<-1>{});
+    }
+    const double dlx = nnd_upwind(m.ux > 0.0, ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1),
+                                  ld(L, 0u, s.xp2));
+    const double dly = nnd_upwind(m.uy > 0.0, ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1),
+                                  ld(L, 0u, s.yp2));
+    double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+    if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
+    st_stream(Lo, 0u, s.c, lnew);
+}
+
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
 // general, or walls meet A_hat and the reaction: the other specialisations then fit without
 // spilling, the compiler stops parking scalar registers in vector lanes, and the wall
@@ -597,6 +734,9 @@ hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, dou
     else if constexpr (MODE == 2)
         hipLaunchKernelGGL((k_step_sf<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
+    else if constexpr (MODE == 3)
+        hipLaunchKernelGGL((k_step_sh<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
+                           st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
     else
         hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND, GHOST>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl, gb);
@@ -635,9 +775,10 @@ hipError_t launch_shape(const Consts* dc, int flags, int nx, int ny, const doubl
 
 // Launch variants compiled in: {tile_x, tile_y, mode}.  mode 0 collides first and reads the
 // stencil straight from the caches; mode 1 collides first and stages each stencil plane in
-// LDS; mode 2 streams first (k_step_sf, each input value read from HBM once).
+// LDS; mode 2 streams first (k_step_sf, each input value read from HBM once); mode 3
+// collides first with the tile's centre values shared in LDS (k_step_sh).
 const int kStepVariants[][3] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}, {256, 2, 0}, {256, 1, 0}, {64, 4, 0},
-                                {64, 4, 2}, {32, 8, 2}, {128, 2, 2}, {256, 1, 2}};
+                                {64, 4, 2}, {32, 8, 2}, {128, 2, 2}, {256, 1, 2}, {64, 4, 3}, {128, 2, 3}};
 const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
 const int kWallTile[2] = {64, 4};   // the one shape compiled with the wall (ghost-layer) stencil
 
@@ -673,6 +814,8 @@ hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny,
         case 7: return launch_shape<32, 8, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         case 8: return launch_shape<128, 2, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         case 9: return launch_shape<256, 1, 2>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 10: return launch_shape<64, 4, 3>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
+        case 11: return launch_shape<128, 2, 3>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
         default: return launch_shape<64, 4, 1>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical, st, bl);
     }
 }

@@ -25,9 +25,9 @@ def _profiled_tiles():
     out = {}
     with open(bench.PMC_FILE) as fh:
         for line in fh:
-            m = re.match(r"kernel k_step(_lds|_sf)?<(\d+),(\d+),\S* .*hbm_bytes_per_launch (\S+)", line)
+            m = re.match(r"kernel k_step(_lds|_sf|_sh)?<(\d+),(\d+),\S* .*hbm_bytes_per_launch (\S+)", line)
             if m:
-                out[(int(m.group(2)), int(m.group(3)), {None: 0, "_lds": 1, "_sf": 2}[m.group(1)])] = float(m.group(4))
+                out[(int(m.group(2)), int(m.group(3)), {None: 0, "_lds": 1, "_sf": 2, "_sh": 3}[m.group(1)])] = float(m.group(4))
     return out
 
 

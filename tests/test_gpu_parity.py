@@ -290,7 +290,7 @@ def test_ragged_and_degenerate_grids(nx, ny, bcx, bcy):
 
 
 VARIANTS = [(64, 4, 1), (32, 8, 1), (128, 2, 1), (256, 2, 0), (256, 1, 0), (64, 4, 0), (64, 4, 2), (32, 8, 2),
-            (128, 2, 2), (256, 1, 2)]
+            (128, 2, 2), (256, 1, 2), (64, 4, 3), (128, 2, 3)]
 
 
 @pytest.mark.parametrize("w", [W.detonation(nx=333, ny=7, steps=30).with_(R=W.rates(100.0, r8=200.0, r9=150.0),
