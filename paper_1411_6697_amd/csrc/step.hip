@@ -158,15 +158,14 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
     local_source<CHEM, GEXP>(c, M, lam, A8, A9, m, h, src, dlam);
 }
 
-// The same from the cell's 24 values already in registers (the stream-first kernel has
-// read them while streaming): lambda and, when A_hat is active, the four neighbours'
+// The same from the cell's 24 values and lambda already in registers (read while
+// streaming, or in the centre burst); when A_hat is active, the four neighbours'
 // velocities are loaded here.
 template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
 __device__ __forceinline__ void cell_source_held(const Consts* __restrict__ c, const Mats& M, const double f[NV],
-                                                 const Soa& L, const Soa& Ui, const Off& s, double src[NV],
-                                                 double& dlam, double& lam, Macro& m) {
+                                                 double lam, const Soa& Ui, const Off& s, double src[NV],
+                                                 double& dlam, Macro& m) {
     if (SRT) {
-        lam = ld(L, 0u, s.c);
         m = macro_sums(c, f);
         srt_source<CHEM, GEXP>(c, M, lam, m, f, src, dlam);
         return;
@@ -176,13 +175,10 @@ __device__ __forceinline__ void cell_source_held(const Consts* __restrict__ c, c
         const uint32_t up = opaque(Ui.plane_bytes);
         const double a0 = ld(Ui, 0u, s.xp1), a1 = ld(Ui, 0u, s.xm1), a2 = ld(Ui, up, s.xp1), a3 = ld(Ui, up, s.xm1);
         const double b0 = ld(Ui, 0u, s.yp1), b1 = ld(Ui, 0u, s.ym1), b2 = ld(Ui, up, s.yp1), b3 = ld(Ui, up, s.ym1);
-        lam = ld(L, 0u, s.c);
         gxx = (a0 - a1) * ro(c->half_inv_dx);   // d u_x / dx
         gyx = (a2 - a3) * ro(c->half_inv_dx);   // d u_y / dx
         gxy = (b0 - b1) * ro(c->half_inv_dy);   // d u_x / dy
         gyy = (b2 - b3) * ro(c->half_inv_dy);   // d u_y / dy
-    } else {
-        lam = ld(L, 0u, s.c);
     }
     Blocks sb, h;
     to_combos(f, sb);
@@ -521,9 +517,10 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
     __builtin_amdgcn_sched_barrier(0);
 
     // Phase B: collision and chemistry, then the update of each plane
-    double src[NV], dlam, lam;
+    double src[NV], dlam;
     Macro m;
-    cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, L, Ui, s, src, dlam, lam, m);
+    const double lam = ld(L, 0u, s.c);
+    cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, lam, Ui, s, src, dlam, m);
     __builtin_amdgcn_sched_barrier(0);
     {
         const uint32_t pb = opaque(G.plane_bytes);
@@ -587,7 +584,7 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
                                                                int vertical, Blend bl) {
     static_assert(TX % 64 == 0, "a wave must hold cells of one row");
     constexpr int NT = TX * TY;
-    __shared__ double cen[NV * NT];
+    __shared__ double cen[(NV + 1) * NT];     // the 24 planes and lambda
     int tx, ty;
     if (!tile_of(blockIdx.x, gx, ntiles, vertical, tx, ty)) return;   // uniform over the work-group
     const int tid = (int)threadIdx.x;
@@ -608,10 +605,11 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
     Macro m{1.0, 0.0, 0.0, 1.0};
     if (inside) {
         double f[NV];
-        load_cell_first(F, s.c, f);
+        load_cell_first(F, s.c, f, &L, &lam);
 #pragma unroll
         for (int i = 0; i < NV; ++i) cen[i * NT + tid] = f[i];
-        cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, L, Ui, s, src, dlam, lam, m);
+        cen[NV * NT + tid] = lam;
+        cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, lam, Ui, s, src, dlam, m);
     }
     __syncthreads();
     if (!inside) return;
@@ -668,26 +666,37 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
             st_stream(Uo, 0u, s.c, va.jx / va.r);
             st_stream(Uo, opaque(Uo.plane_bytes), s.c, va.jy / va.r);
         }
+        // lambda, upwind by the sign of u, from the same sources
+        const double* lslot = cen + NV * NT + tid;
+        double dlx;
+        if (XL) {
+            const XNeighbours n = x_neighbours(lam, ld(L, 0u, halo), lane);
+            dlx = nnd_upwind(m.ux > 0.0, n.m2, n.m1, lam, n.p1, n.p2);
+        } else {
+            dlx = nnd_upwind(m.ux > 0.0, ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
+        }
+        const double dly = nnd_upwind(m.uy > 0.0, centre_or_load<IM2>(lslot, -2 * TX, L, 0u, s.ym2),
+                                      centre_or_load<IM1>(lslot, -TX, L, 0u, s.ym1), lam,
+                                      centre_or_load<IP1>(lslot, TX, L, 0u, s.yp1),
+                                      centre_or_load<IP2>(lslot, 2 * TX, L, 0u, s.yp2));
+        double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
+        if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
+        st_stream(Lo, 0u, s.c, lnew);
     };
     const int rw = __builtin_amdgcn_readfirstlane(tid / TX);
     if (lanes_form_row && y >= 2 && y + 2 < ny) {
-        static_assert(TY <= 4, "rows of the tile are specialised up to four");
+        static_assert(TY <= 6, "rows of the tile are specialised up to six");
         if (rw == 0) phase2(std::true_type{}, RowOf<0>{});
         else if (TY > 1 && rw == 1) phase2(std::true_type{}, RowOf<(TY > 1 ? 1 : 0)>{});
         else if (TY > 2 && rw == 2) phase2(std::true_type{}, RowOf<(TY > 2 ? 2 : 0)>{});
-        else if (TY > 3) phase2(std::true_type{}, RowOf<(TY > 3 ? 3 : 0)>{});
+        else if (TY > 3 && rw == 3) phase2(std::true_type{}, RowOf<(TY > 3 ? 3 : 0)>{});
+        else if (TY > 4 && rw == 4) phase2(std::true_type{}, RowOf<(TY > 4 ? 4 : 0)>{});
+        else if (TY > 5) phase2(std::true_type{}, RowOf<(TY > 5 ? 5 : 0)>{});
     } else if (lanes_form_row) {
         phase2(std::true_type{}, RowOf<-1>{});
     } else {
         phase2(std::false_type{}, RowOf<-1>{});
     }
-    const double dlx = nnd_upwind(m.ux > 0.0, ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1),
-                                  ld(L, 0u, s.xp2));
-    const double dly = nnd_upwind(m.uy > 0.0, ld(L, 0u, s.ym2), ld(L, 0u, s.ym1), lam, ld(L, 0u, s.yp1),
-                                  ld(L, 0u, s.yp2));
-    double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
-    if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
-    st_stream(Lo, 0u, s.c, lnew);
 }
 
 // At least three waves per SIMD (a budget of 168 registers) unless the rate exponents are
