@@ -100,13 +100,22 @@ struct StreamConsts {
     double wx[3];                               // Courant numbers dt v_g / dx of the groups
 };
 
-// one step of one cell of a 1D instance (x-derivatives only; y-differences are zero)
+// one step of one cell of a 1D instance (x-derivatives only; y-differences are zero).
+// [lo, hi] is the instance, cells below `end` are updated in this pass of the work-group,
+// stash holds this thread's 24 LDS slots ([plane][kBatchThreads]).
 template <bool AMOD, bool CHEM, bool GEXP>
 __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const StreamConsts& k,
-                                        const BatchInst* __restrict__ I, int lo, int hi, int j, const Soa& F,
-                                        const Soa& G, const Soa& L, const Soa& Lo, const Soa& Ui,
-                                        const Soa& Uo) {
+                                        const BatchInst* __restrict__ I, int lo, int hi, int end, int j,
+                                        const Soa& F, const Soa& G, const Soa& L, const Soa& Lo, const Soa& Ui,
+                                        const Soa& Uo, double* stash) {
     const uint32_t oc = (uint32_t)j * 8u;
+    // A wave updates 64 consecutive cells; when they and their two neighbours on each side
+    // lie inside the instance, the x-stencil of a plane is the centre values of the
+    // neighbouring lanes plus one halo load (the two cells beyond each end), and each lane
+    // keeps its centre values in its own LDS slots between the collision and the streaming.
+    const int lane = (int)(threadIdx.x & 63u);
+    const int j0 = j - lane;
+    const bool by_lanes = j0 - 2 >= lo && j0 + 65 <= hi && j0 + 64 <= end;     // uniform per wave
     const uint32_t om2 = (uint32_t)max(j - 2, lo) * 8u, om1 = (uint32_t)max(j - 1, lo) * 8u;
     const uint32_t op1 = (uint32_t)min(j + 1, hi) * 8u, op2 = (uint32_t)min(j + 2, hi) * 8u;
 
@@ -122,6 +131,10 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
         }
         double f[NV];
         load_cell(F, oc, f);
+        if (by_lanes) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) stash[i * kBatchThreads] = f[i];
+        }
         Blocks sb, h;
         to_combos(f, sb);
         forward(c->mat, sb, h);
@@ -157,38 +170,78 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
             p.v[4] = ld(F, so, op2);
         }
     };
-    VelAcc va;                                  // velocity of the new state (for A_hat)
-    PlaneLoads cur, nxt;
-    double lm2 = 0.0, lm1 = 0.0, lp1 = 0.0, lp2 = 0.0;
-    load_plane(0, cur);
+    auto by_loads = [&]() {
+        VelAcc va;                              // velocity of the new state (for A_hat)
+        PlaneLoads cur, nxt;
+        double lm2 = 0.0, lm1 = 0.0, lp1 = 0.0, lp2 = 0.0;
+        load_plane(0, cur);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        if (i + 1 < NV) {
-            load_plane(i + 1, nxt);
-        } else {
-            lm2 = ld(L, 0u, om2);
-            lm1 = ld(L, 0u, om1);
-            lp1 = ld(L, 0u, op1);
-            lp2 = ld(L, 0u, op2);
+        for (int i = 0; i < NV; ++i) {
+            if (i + 1 < NV) {
+                load_plane(i + 1, nxt);
+            } else {
+                lm2 = ld(L, 0u, om2);
+                lm1 = ld(L, 0u, om1);
+                lp1 = ld(L, 0u, op1);
+                lp2 = ld(L, 0u, op2);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const int g = i / 8, d = i % 8;
+            const double wx = k.wx[g];                // Courant number of the group
+            const double f0 = cur.v[2];
+            double a = f0;
+            if (DUX[d] > 0) a = fma(-wx, nnd_pos(cur.v[0], cur.v[1], f0, cur.v[3]), a);
+            if (DUX[d] < 0) a = fma(wx, nnd_neg(cur.v[1], f0, cur.v[3], cur.v[4]), a);
+            double out = fma(dt, src[i], a);
+            if (AMOD) vel_add(va, k.vg[g], d, out);
+            st(G, (uint32_t)i * pb, oc, out);
+            cur = nxt;
         }
-        __builtin_amdgcn_sched_barrier(0);
-        const int g = i / 8, d = i % 8;
-        const double wx = k.wx[g];                    // Courant number of the group
-        const double f0 = cur.v[2];
-        double a = f0;
-        if (DUX[d] > 0) a = fma(-wx, nnd_pos(cur.v[0], cur.v[1], f0, cur.v[3]), a);
-        if (DUX[d] < 0) a = fma(wx, nnd_neg(cur.v[1], f0, cur.v[3], cur.v[4]), a);
-        double out = fma(dt, src[i], a);
-        if (AMOD) vel_add(va, k.vg[g], d, out);
-        st(G, (uint32_t)i * pb, oc, out);
-        cur = nxt;
-    }
-    if (AMOD) {
-        st(Uo, 0u, oc, va.jx / va.r);
-        st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
-    }
-    const double dlx = nnd_upwind(m.ux > 0.0, lm2, lm1, lam, lp1, lp2);
-    st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
+        if (AMOD) {
+            st(Uo, 0u, oc, va.jx / va.r);
+            st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
+        }
+        const double dlx = nnd_upwind(m.ux > 0.0, lm2, lm1, lam, lp1, lp2);
+        st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
+    };
+    auto from_lanes = [&]() {
+        const uint32_t halo = (uint32_t)(lane < 32 ? (lane == 0 ? j0 - 2 : j0 - 1) : (lane == 63 ? j0 + 65 : j0 + 64)) * 8u;
+        VelAcc va;
+        double hcur = ld(F, 0u, halo), hnxt = 0.0, hlam = 0.0;    // plane 0 moves along x
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i + 1 < NV) {
+                if (DUX[(i + 1) & 7] != 0) hnxt = ld(F, (uint32_t)(i + 1) * pb, halo);
+            } else {
+                hlam = ld(L, 0u, halo);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const int g = i / 8, d = i % 8;
+            const double wx = k.wx[g];
+            const double f0 = stash[i * kBatchThreads];
+            double a = f0;
+            if (DUX[d] != 0) {
+                const XNeighbours n = x_neighbours(f0, hcur, lane);
+                if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
+                if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
+            }
+            double out = fma(dt, src[i], a);
+            if (AMOD) vel_add(va, k.vg[g], d, out);
+            st(G, (uint32_t)i * pb, oc, out);
+            hcur = hnxt;
+        }
+        if (AMOD) {
+            st(Uo, 0u, oc, va.jx / va.r);
+            st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
+        }
+        const XNeighbours n = x_neighbours(lam, hlam, lane);
+        const double dlx = nnd_upwind(m.ux > 0.0, n.m2, n.m1, lam, n.p1, n.p2);
+        st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
+    };
+    if (by_lanes)
+        from_lanes();
+    else
+        by_loads();
 }
 
 template <bool AMOD, bool CHEM, bool GEXP>
@@ -206,6 +259,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
     const int w = nwg >= 8 ? (b8 % 8) * (nwg / 8) + b8 / 8 : b8;
     const int sbeg = wg_seg[w], send = wg_seg[w + 1];
     __shared__ int32_t stop;
+    __shared__ double stash[NV * kBatchThreads];       // each thread's centre values (own slots)
     // the descriptors are swapped after every step (selecting them by step parity inside
     // the loop would turn them into per-lane values)
     StreamConsts k;
@@ -239,7 +293,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
             // uniform trip count; the tail is masked
             for (int base = S.begin; base < S.end; base += kBatchThreads) {
                 const int j = base + (int)threadIdx.x;
-                if (j < S.end) cell_1d<AMOD, CHEM, GEXP>(c, k, I, S.lo, S.hi, j, F, G, L, Lo, Ui, Uo);
+                if (j < S.end)
+                    cell_1d<AMOD, CHEM, GEXP>(c, k, I, S.lo, S.hi, S.end, j, F, G, L, Lo, Ui, Uo,
+                                              stash + threadIdx.x);
             }
         }
         // The barrier orders every thread's stores before thread 0's release (cumulative),

@@ -394,41 +394,6 @@ __device__ __forceinline__ bool tile_of(int b, int gx, int ntiles, int vertical,
     return true;
 }
 
-// Lane moves of a double across the wave (DPP): lane i receives lane i-1's value
-// (from_left) or lane i+1's (from_right); the end lane keeps 0 and is patched by the caller.
-__device__ __forceinline__ double from_left(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);   // wave_shr:1
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double from_right(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);   // wave_shl:1
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-// The x-neighbours of one plane for a wave that holds 64 consecutive cells of a row, from
-// the centre values of the neighbouring lanes.  h is the plane's halo: lanes 0-31 hold the
-// value at x0-1 (lane 0: x0-2), lanes 32-63 the value at x0+64 (lane 63: x0+65), x0 being
-// the wave's first cell, each index under the boundary rule.
-struct XNeighbours {
-    double m2, m1, p1, p2;
-};
-__device__ __forceinline__ XNeighbours x_neighbours(double f0, double h, int lane) {
-    const double l1 = from_left(f0), r1 = from_right(f0);
-    const double l2 = from_left(l1), r2 = from_right(r1);
-    // every lane takes part in the halo load (left to itself the compiler would load it on
-    // the end lanes only, behind a branch and a wait per plane)
-    asm("" : "+v"(h));
-    const double hl = from_right(h), hr = from_left(h);
-    XNeighbours n;
-    n.m2 = lane < 2 ? h : l2;
-    n.m1 = lane == 0 ? hl : l1;     // lane 0: x0-1, held by lane 1
-    n.p1 = lane == 63 ? hr : r1;    // lane 63: x0+64, held by lane 62
-    n.p2 = lane >= 62 ? h : r2;
-    return n;
-}
-
 // Stream-first step: every value of the input state is read from HBM once.  Phase A walks
 // the 24 planes, reading each plane's centre value with its NND stencil, and keeps the
 // streamed value f_i - dt v_i . grad_NND f_i in this thread's slots of LDS and the 24
