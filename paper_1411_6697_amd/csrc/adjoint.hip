@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "lbkm_abi_internal.h"
 #include "lbkm_device.h"
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_local(const Consts* __restr
     }
 }
 
-__global__ __launch_bounds__(kAdjThreads, 3) void k_adj_stream(const Consts* __restrict__ c,
+__global__ __launch_bounds__(kAdjThreads, 2) void k_adj_stream(const Consts* __restrict__ c,
                                                             const double* __restrict__ f,
                                                             const double* __restrict__ lam,
                                                             const double* __restrict__ af1,
@@ -596,56 +597,90 @@ __global__ __launch_bounds__(kAdjThreads, 3) void k_adj_stream(const Consts* __r
     // barrier keeps them there), so each plane's memory latency hides behind the previous
     // plane's arithmetic; all 24 updates are formed before any store into af0, which would
     // otherwise hold the following loads behind it.
+    // Where the wave's 64 cells and two more on each side lie inside the row, the x-stencils
+    // of f and a^{n+1} are the centre values of the neighbouring lanes plus one halo load
+    // each (the two cells beyond each end of the wave), instead of five gathers each.
     struct PlaneLoads {
         double fx[5], ax[5], fy[5], ay[5];   // f and a^{n+1} at offsets -2..2 along x and y
+        double hf, ha;                       // the halo values of f and a^{n+1} (lane moves)
     };
-    auto load_plane = [&](int i, PlaneLoads& p) {
-        const uint32_t so = (uint32_t)i * pb;
-        const int d = i & 7;
-        if (DUX[d] != 0) {
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                p.fx[t] = ld(Fb, so, bx[t]);
-                p.ax[t] = ld(Ab, so, bx[t]);
-            }
-        }
-        if (DUY[d] != 0) {
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                p.fy[t] = ld(Fb, so, by[t]);
-                p.ay[t] = ld(Ab, so, by[t]);
-            }
-        }
-    };
+    const int lane = (int)(threadIdx.x & 63u);
+    const int x0 = x - lane;
+    const bool by_lanes = x0 >= 2 && x0 + 66 <= nx;      // uniform per wave
+    const uint32_t bh = (uint32_t)(row + (lane < 32 ? (lane == 0 ? x0 - 2 : x0 - 1) : (lane == 63 ? x0 + 65 : x0 + 64))) * 8u;
     __shared__ double upd_s[NV][kAdjThreads];   // this thread's 24 updates (own slots only)
-    PlaneLoads cur, nxt;
-    load_plane(0, cur);
+    auto run = [&](auto from_lanes) {
+        constexpr bool XL = decltype(from_lanes)::value;
+        auto load_plane = [&](int i, PlaneLoads& p) {
+            const uint32_t so = (uint32_t)i * pb;
+            const int d = i & 7;
+            if (DUX[d] != 0) {
+                if (XL) {
+                    p.fx[2] = ld(Fb, so, bc);
+                    p.ax[2] = ld(Ab, so, bc);
+                    p.hf = ld(Fb, so, bh);
+                    p.ha = ld(Ab, so, bh);
+                } else {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        if (i + 1 < NV) load_plane(i + 1, nxt);
-        __builtin_amdgcn_sched_barrier(0);
-        const int g = i / 8, d = i % 8;
-        const double vg = c->vg[g];
-        double acc = 0.0, a_c = 0.0;          // a_c: a^{n+1} of this cell (offset 0 of a stencil)
-        if (DUX[d] != 0) {
-            double av[5];
+                    for (int t = 0; t < 5; ++t) {
+                        p.fx[t] = ld(Fb, so, bx[t]);
+                        p.ax[t] = ld(Ab, so, bx[t]);
+                    }
+                }
+            }
+            if (DUY[d] != 0) {
 #pragma unroll
-            for (int t = 0; t < 5; ++t) av[t] = AX.val[t] * cur.ax[t];
-            acc += vg * DUX[d] * c->inv_dx * nnd_t(AX, cur.fx, av, DUX[d]);
-            a_c = cur.ax[2];
+                for (int t = 0; t < 5; ++t) {
+                    p.fy[t] = ld(Fb, so, by[t]);
+                    p.ay[t] = ld(Ab, so, by[t]);
+                }
+            }
+        };
+        PlaneLoads cur, nxt;
+        load_plane(0, cur);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i + 1 < NV) load_plane(i + 1, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+            const int g = i / 8, d = i % 8;
+            const double vg = ro(c->vg[g]);
+            double acc = 0.0, a_c = 0.0;          // a_c: a^{n+1} of this cell (offset 0 of a stencil)
+            if (DUX[d] != 0) {
+                if (XL) {
+                    const XNeighbours nf = x_neighbours(cur.fx[2], cur.hf, lane);
+                    const XNeighbours na = x_neighbours(cur.ax[2], cur.ha, lane);
+                    cur.fx[0] = nf.m2;
+                    cur.fx[1] = nf.m1;
+                    cur.fx[3] = nf.p1;
+                    cur.fx[4] = nf.p2;
+                    cur.ax[0] = na.m2;
+                    cur.ax[1] = na.m1;
+                    cur.ax[3] = na.p1;
+                    cur.ax[4] = na.p2;
+                }
+                double av[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t) av[t] = AX.val[t] * cur.ax[t];
+                acc += vg * DUX[d] * ro(c->inv_dx) * nnd_t(AX, cur.fx, av, DUX[d]);
+                a_c = cur.ax[2];
+            }
+            if (DUY[d] != 0) {
+                double av[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t) av[t] = AY.val[t] * cur.ay[t];
+                acc += vg * DUY[d] * ro(c->inv_dy) * nnd_t(AY, cur.fy, av, DUY[d]);
+                a_c = cur.ay[2];
+            }
+            const double vx = vg * DUX[d], vy = vg * DUY[d];
+            const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + ro(c->eta2[g])) * hb4;
+            upd_s[i][threadIdx.x] = a_c - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
+            cur = nxt;
         }
-        if (DUY[d] != 0) {
-            double av[5];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) av[t] = AY.val[t] * cur.ay[t];
-            acc += vg * DUY[d] * c->inv_dy * nnd_t(AY, cur.fy, av, DUY[d]);
-            a_c = cur.ay[2];
-        }
-        const double vx = vg * DUX[d], vy = vg * DUY[d];
-        const double mt = hb1 + vx * hb2 + vy * hb3 + (vx * vx + vy * vy + c->eta2[g]) * hb4;
-        upd_s[i][threadIdx.x] = a_c - dt * acc + (vx - ux) * cx_n + (vy - uy) * cy_n + mt;
-        cur = nxt;
-    }
+    };
+    if (by_lanes)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 
     // transposed advection of lambda: D lambda at cell j is upwinded by the sign of u(j)
     auto lam_t = [&](const AxisAdj& A, const int64_t o[5], const double* __restrict__ Ua, double inv) {

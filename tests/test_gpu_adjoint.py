@@ -87,7 +87,10 @@ def _param_close(g, ref, tol, label):
 
 CASES = [  # nx, ny, bc_x, bc_y
     (40, 6, "outflow", "periodic"), (9, 7, "periodic", "outflow"), (1, 4, "outflow", "periodic"),
-    (2, 3, "periodic", "periodic"), (3, 1, "outflow", "outflow"), (5, 2, "outflow", "outflow")]
+    (2, 3, "periodic", "periodic"), (3, 1, "outflow", "outflow"), (5, 2, "outflow", "outflow"),
+    # rows wide enough for waves whose x-stencils come from neighbouring lanes (interior
+    # waves of a 256-wide work-group), beside waves at the row ends that gather them
+    (300, 3, "outflow", "periodic"), (200, 2, "periodic", "outflow")]
 
 
 @pytest.mark.parametrize("nx,ny,bcx,bcy,mn", [c + ((1.0, 1.0),) for c in CASES] +
