@@ -158,8 +158,8 @@ lbkm_status lbkm_set_state(lbkm_ctx* ctx, const double* f, const double* lam);
  * (each input value is read once: the streamed values wait in LDS while the cell collides
  * from its centre values); 3 collides first with the tile's centre values shared in LDS
  * (the streaming reads in-tile neighbours from LDS and neighbouring lanes, and loads only
- * the halo).  Compiled shapes: (64,4,0) (default), (256,2,0), (256,1,0), (64,4,1),
- * (32,8,1), (128,2,1), (64,4,2), (32,8,2), (128,2,2), (256,1,2), (64,4,3), (128,2,3);
+ * the halo).  Compiled shapes: (64,4,0), (256,2,0), (256,1,0), (64,4,1), (32,8,1),
+ * (128,2,1), (64,4,2), (32,8,2), (128,2,2), (256,1,2), (64,4,3) (default), (128,2,3);
  * LBKM_EINVAL for any other.  Results do not depend on the launch shape (bitwise). */
 lbkm_status lbkm_set_tile(lbkm_ctx* ctx, int32_t tile_x, int32_t tile_y, int32_t lds);
 

@@ -22,8 +22,8 @@ struct lbkm_ctx {
     double* lam[2] = {nullptr, nullptr};
     int64_t pitch = 0;
     int cur = 0;
-    int step_variant = 5;              // launch shape of the step kernel (kStepVariants): 64x4, collide first,
-                                       // direct stencil loads (the fastest on MI355X at 2048^2)
+    int step_variant = 10;             // launch shape of the step kernel (kStepVariants): 64x4, collide first,
+                                       // centre values shared in LDS (the fastest on MI355X at 2048^2)
     int tile_order = 1;                // 1: bands of tile columns per XCD, 0: bands of tile rows
     bool bound = false, params = false, fields = false;
     int64_t steps = 0;
