@@ -196,7 +196,7 @@ lbkm_status lbkm_set_srt(lbkm_ctx* ctx, double tau);
  *           edge cell's non-equilibrium part f - f^eq; lambda copies the edge cell.
  * state: host array of 5 doubles (used by types 2 and 3; may be NULL for 0 and 1).  A wall
  * needs bc = LBKM_BC_OUTFLOW on its axis (the opposite side keeps that rule unless it is a
- * wall too).  With a wall the step uses the 64 x 4 direct launch shape.  Errors: EINVAL
+ * wall too).  With a wall the step uses the 64 x 4 shared-centre launch shape.  Errors: EINVAL
  * for a bad side, type, axis rule or state (non-finite, rho <= 0 or T <= 0), or when the
  * library-owned ghost layers (27 * 8 * max(nx, ny) doubles) would exceed 4 GiB; ESTATE on
  * a batched context.  lbkm_adjoint_step refuses a context with walls (ESTATE). */
@@ -218,7 +218,7 @@ lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order);
 /* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
  * orders for a few steps from the current state, keeps the fastest, and restores the
  * state and the step count (the trial steps run on the bound buffers; a temporary copy
- * of the state is allocated).  With wall sides there is one shape (64 x 4, direct) and
+ * of the state is allocated).  With wall sides there is one shape (64 x 4, shared centres) and
  * only the two tile orders are timed.  Needs parameters and fields.  choice (host, 4 ints, may be NULL)
  * receives tile_x, tile_y, lds, vertical.  Synchronous. */
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice);

@@ -539,11 +539,12 @@ lbkm_status lbkm_set_tile_order(lbkm_ctx* ctx, int32_t vertical) {
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;
-    // wall sides run one shape (kWallTile, direct loads): only the tile order is tuned
+    // wall sides run one shape (kWallTile): only the tile order is tuned
     int v_lo = 0, v_hi = kNumStepVariants;
     if (any_wall(ctx))
         for (int v = 0; v < kNumStepVariants; ++v)
-            if (kStepVariants[v][0] == kWallTile[0] && kStepVariants[v][1] == kWallTile[1] && kStepVariants[v][2] == 0) {
+            if (kStepVariants[v][0] == kWallTile[0] && kStepVariants[v][1] == kWallTile[1] &&
+                kStepVariants[v][2] == kWallTile[2]) {
                 v_lo = v;
                 v_hi = v + 1;
             }

@@ -9,7 +9,7 @@ namespace lbkm {
 
 extern const int kStepVariants[][3];   // {tile_x, tile_y, mode} per launch variant (step.hip)
 extern const int kNumStepVariants;
-extern const int kWallTile[2];          // {tile_x, tile_y} of the wall specialisation (direct loads)
+extern const int kWallTile[3];          // {tile_x, tile_y, mode} of the wall specialisation
 int step_flags(const Consts& c);        // compile-time specialisation of the step kernel
 // vertical != 0: XCD-contiguous bands of tile columns (when the tile columns divide by
 // eight), else bands of tile rows
@@ -25,8 +25,8 @@ struct Blend {
     double a, b;
 };
 // bl == nullptr: a plain forward-Euler step.  gb != nullptr: some side is a wall; gb holds
-// the ghost layers of the input state (launch_ghost) and the kWallTile (64 x 4) direct shape
-// is used.
+// the ghost layers of the input state (launch_ghost) and the kWallTile (64 x 4 shared-centre)
+// shape is used.
 hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny, const double* fin,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
                        int vertical, hipStream_t st, const Blend* bl = nullptr, const double* gb = nullptr);

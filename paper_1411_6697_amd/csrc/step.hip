@@ -161,17 +161,26 @@ __device__ __forceinline__ void cell_source(const Consts* __restrict__ c, const 
 // The same from the cell's 24 values and lambda already in registers (read while
 // streaming, or in the centre burst); when A_hat is active, the four neighbours'
 // velocities are loaded here.
-template <bool AMOD, bool CHEM, bool GEXP, bool SRT>
+template <bool AMOD, bool CHEM, bool GEXP, bool SRT, bool GHOST = false>
 __device__ __forceinline__ void cell_source_held(const Consts* __restrict__ c, const Mats& M, const double f[NV],
                                                  double lam, const Soa& Ui, const Off& s, double src[NV],
-                                                 double& dlam, Macro& m) {
+                                                 double& dlam, Macro& m, const Soa* Gb = nullptr,
+                                                 const Ghosts* gh = nullptr) {
     if (SRT) {
         m = macro_sums(c, f);
         srt_source<CHEM, GEXP>(c, M, lam, m, f, src, dlam);
         return;
     }
     double gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
-    if (AMOD) {
+    if (AMOD && GHOST) {
+        // velocities of the ghost points come from the ghost buffer's velocity planes
+        const uint32_t up = opaque(Ui.plane_bytes), gp = opaque(Gb->plane_bytes);
+        const uint32_t gx0 = (NV + 1) * gp, gy0 = (NV + 2) * gp;
+        gxx = (sld<true>(Ui, 0u, s.xp1, *Gb, gx0, *gh, 2) - sld<true>(Ui, 0u, s.xm1, *Gb, gx0, *gh, 1)) * ro(c->half_inv_dx);
+        gyx = (sld<true>(Ui, up, s.xp1, *Gb, gy0, *gh, 2) - sld<true>(Ui, up, s.xm1, *Gb, gy0, *gh, 1)) * ro(c->half_inv_dx);
+        gxy = (sld<true>(Ui, 0u, s.yp1, *Gb, gx0, *gh, 6) - sld<true>(Ui, 0u, s.ym1, *Gb, gx0, *gh, 5)) * ro(c->half_inv_dy);
+        gyy = (sld<true>(Ui, up, s.yp1, *Gb, gy0, *gh, 6) - sld<true>(Ui, up, s.ym1, *Gb, gy0, *gh, 5)) * ro(c->half_inv_dy);
+    } else if (AMOD) {
         const uint32_t up = opaque(Ui.plane_bytes);
         const double a0 = ld(Ui, 0u, s.xp1), a1 = ld(Ui, 0u, s.xm1), a2 = ld(Ui, up, s.xp1), a3 = ld(Ui, up, s.xm1);
         const double b0 = ld(Ui, 0u, s.yp1), b1 = ld(Ui, 0u, s.ym1), b2 = ld(Ui, up, s.yp1), b3 = ld(Ui, up, s.ym1);
@@ -529,24 +538,23 @@ struct RowOf {
     static constexpr int value = RW;
 };
 
-template <bool IN>
+template <bool IN, bool GH = false>
 __device__ __forceinline__ double centre_or_load(const double* slot, int delta, const Soa& F, uint32_t so,
-                                                 uint32_t off) {
+                                                 uint32_t off, const Soa* Gb = nullptr, uint32_t sg = 0u,
+                                                 const Ghosts* gh = nullptr, int k = 0) {
     if constexpr (IN)
         return slot[delta];
+    else if constexpr (GH)
+        return sld<true>(F, so, off, *Gb, sg, *gh, k);
     else
         return ld(F, so, off);
 }
 
-template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND>
-__global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts* __restrict__ c,
-                                                               const double* __restrict__ fin,
-                                                               double* __restrict__ fout,
-                                                               const double* __restrict__ lin,
-                                                               double* __restrict__ lout,
-                                                               const double* __restrict__ uin,
-                                                               double* __restrict__ uout, int gx, int ntiles,
-                                                               int vertical, Blend bl) {
+template <int TX, int TY, bool AMOD, bool CHEM, bool GEXP, bool SRT, bool BLEND, bool GHOST>
+__global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3) void k_step_sh(
+        const Consts* __restrict__ c, const double* __restrict__ fin, double* __restrict__ fout,
+        const double* __restrict__ lin, double* __restrict__ lout, const double* __restrict__ uin,
+        double* __restrict__ uout, int gx, int ntiles, int vertical, Blend bl, const double* __restrict__ gb) {
     static_assert(TX % 64 == 0, "a wave must hold cells of one row");
     constexpr int NT = TX * TY;
     __shared__ double cen[(NV + 1) * NT];     // the 24 planes and lambda
@@ -564,6 +572,11 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
     const Soa Ln = soa(BLEND ? (bl.ln ? bl.ln : lout) : lin, 0);
     const Off s = stencil_offsets(c, inside ? x : 0, inside ? y : 0);
     const double dt = ro(c->dt), idx_ = ro(c->inv_dx), idy = ro(c->inv_dy);
+    // wall sides: the ghost buffer and which stencil points read it
+    const Soa Gb = soa(GHOST ? gb : fin, 8 * (int64_t)ro(c->gL));
+    Ghosts gh;
+    gh.is = 0u;
+    if (GHOST && inside) gh = ghosts_of(c, x, y);
 
     // Phase 1: centre burst, the values to LDS, collision and chemistry
     double src[NV], dlam = 0.0, lam = 0.0;
@@ -574,7 +587,7 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
 #pragma unroll
         for (int i = 0; i < NV; ++i) cen[i * NT + tid] = f[i];
         cen[NV * NT + tid] = lam;
-        cell_source_held<AMOD, CHEM, GEXP, SRT>(c, c->mat, f, lam, Ui, s, src, dlam, m);
+        cell_source_held<AMOD, CHEM, GEXP, SRT, GHOST>(c, c->mat, f, lam, Ui, s, src, dlam, m, &Gb, &gh);
     }
     __syncthreads();
     if (!inside) return;
@@ -588,9 +601,10 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
         const int hx = lane < 32 ? (lane == 0 ? x0 - 2 : x0 - 1) : (lane == 63 ? x0 + 65 : x0 + 64);
         halo = ((uint32_t)y * (uint32_t)ro(c->pitch) + (uint32_t)wrap(hx, nx, ro(c->bc_x))) * 8u;
     }
-    auto phase2 = [&](auto by_lanes, auto row) {
+    auto phase2 = [&](auto by_lanes, auto row, auto ghost_on) {
         constexpr bool XL = decltype(by_lanes)::value;
         constexpr int RW = decltype(row)::value;   // row of the tile, -1: load every y-neighbour
+        constexpr bool GH = decltype(ghost_on)::value;   // stencil points may lie on wall ghost layers
         constexpr bool IM2 = RW >= 2, IM1 = RW >= 1, IP1 = RW >= 0 && RW + 1 < TY, IP2 = RW >= 0 && RW + 2 < TY;
         const uint32_t pb = opaque(F.plane_bytes);
         VelAcc va;                                  // velocity of the new state (for A_hat)
@@ -604,23 +618,25 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
                 const uint32_t so = (uint32_t)i * pb;
                 const double* slot = cen + i * NT + tid;
                 const double f0 = slot[0];
+                const uint32_t sg = GH ? (uint32_t)i * Gb.plane_bytes : 0u;
+                auto at = [&](uint32_t off, int k) { return sld<GH>(F, so, off, Gb, sg, gh, k); };
                 double a = f0;
                 if (XL && DUX[d] != 0) {
                     const XNeighbours n = x_neighbours(f0, ld(F, so, halo), lane);
                     if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
                     if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
                 } else {
-                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(ld(F, so, s.xm2), ld(F, so, s.xm1), f0, ld(F, so, s.xp1)), a);
-                    if (DUX[d] < 0) a = fma(wx, nnd_neg(ld(F, so, s.xm1), f0, ld(F, so, s.xp1), ld(F, so, s.xp2)), a);
+                    if (DUX[d] > 0) a = fma(-wx, nnd_pos(at(s.xm2, 0), at(s.xm1, 1), f0, at(s.xp1, 2)), a);
+                    if (DUX[d] < 0) a = fma(wx, nnd_neg(at(s.xm1, 1), f0, at(s.xp1, 2), at(s.xp2, 3)), a);
                 }
                 if (DUY[d] > 0)
-                    a = fma(-wy, nnd_pos(centre_or_load<IM2>(slot, -2 * TX, F, so, s.ym2),
-                                         centre_or_load<IM1>(slot, -TX, F, so, s.ym1), f0,
-                                         centre_or_load<IP1>(slot, TX, F, so, s.yp1)), a);
+                    a = fma(-wy, nnd_pos(centre_or_load<IM2, GH>(slot, -2 * TX, F, so, s.ym2, &Gb, sg, &gh, 4),
+                                         centre_or_load<IM1, GH>(slot, -TX, F, so, s.ym1, &Gb, sg, &gh, 5), f0,
+                                         centre_or_load<IP1, GH>(slot, TX, F, so, s.yp1, &Gb, sg, &gh, 6)), a);
                 if (DUY[d] < 0)
-                    a = fma(wy, nnd_neg(centre_or_load<IM1>(slot, -TX, F, so, s.ym1), f0,
-                                        centre_or_load<IP1>(slot, TX, F, so, s.yp1),
-                                        centre_or_load<IP2>(slot, 2 * TX, F, so, s.yp2)), a);
+                    a = fma(wy, nnd_neg(centre_or_load<IM1, GH>(slot, -TX, F, so, s.ym1, &Gb, sg, &gh, 5), f0,
+                                        centre_or_load<IP1, GH>(slot, TX, F, so, s.yp1, &Gb, sg, &gh, 6),
+                                        centre_or_load<IP2, GH>(slot, 2 * TX, F, so, s.yp2, &Gb, sg, &gh, 7)), a);
                 double out = fma(dt, src[i], a);
                 if (BLEND) out = fma(bl.a, ld(Fn, so, s.c), bl.b * out);   // one rounding order in every variant
                 if (AMOD) vel_add(va, c, g, d, out);
@@ -633,34 +649,41 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sh(const Consts*
         }
         // lambda, upwind by the sign of u, from the same sources
         const double* lslot = cen + NV * NT + tid;
+        const uint32_t sl = GH ? NV * Gb.plane_bytes : 0u;
+        auto lat = [&](uint32_t off, int k) { return sld<GH>(L, 0u, off, Gb, sl, gh, k); };
         double dlx;
         if (XL) {
             const XNeighbours n = x_neighbours(lam, ld(L, 0u, halo), lane);
             dlx = nnd_upwind(m.ux > 0.0, n.m2, n.m1, lam, n.p1, n.p2);
         } else {
-            dlx = nnd_upwind(m.ux > 0.0, ld(L, 0u, s.xm2), ld(L, 0u, s.xm1), lam, ld(L, 0u, s.xp1), ld(L, 0u, s.xp2));
+            dlx = nnd_upwind(m.ux > 0.0, lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
         }
-        const double dly = nnd_upwind(m.uy > 0.0, centre_or_load<IM2>(lslot, -2 * TX, L, 0u, s.ym2),
-                                      centre_or_load<IM1>(lslot, -TX, L, 0u, s.ym1), lam,
-                                      centre_or_load<IP1>(lslot, TX, L, 0u, s.yp1),
-                                      centre_or_load<IP2>(lslot, 2 * TX, L, 0u, s.yp2));
+        const double dly = nnd_upwind(m.uy > 0.0, centre_or_load<IM2, GH>(lslot, -2 * TX, L, 0u, s.ym2, &Gb, sl, &gh, 4),
+                                      centre_or_load<IM1, GH>(lslot, -TX, L, 0u, s.ym1, &Gb, sl, &gh, 5), lam,
+                                      centre_or_load<IP1, GH>(lslot, TX, L, 0u, s.yp1, &Gb, sl, &gh, 6),
+                                      centre_or_load<IP2, GH>(lslot, 2 * TX, L, 0u, s.yp2, &Gb, sl, &gh, 7));
         double lnew = lam + dlam - dt * (m.ux * (dlx * idx_) + m.uy * (dly * idy));
         if (BLEND) lnew = fma(bl.a, ld(Ln, 0u, s.c), bl.b * lnew);
         st_stream(Lo, 0u, s.c, lnew);
     };
     const int rw = __builtin_amdgcn_readfirstlane(tid / TX);
-    if (lanes_form_row && y >= 2 && y + 2 < ny) {
+    const std::false_type no_ghost{};
+    // only waves with a stencil point on a wall's ghost layer take the selecting path (those
+    // lie within two cells of a wall side, so every other wave takes the paths below)
+    if (GHOST && __ballot(gh.is != 0u) != 0ull) {
+        phase2(std::false_type{}, RowOf<-1>{}, std::bool_constant<GHOST>{});
+    } else if (lanes_form_row && y >= 2 && y + 2 < ny) {
         static_assert(TY <= 6, "rows of the tile are specialised up to six");
-        if (rw == 0) phase2(std::true_type{}, RowOf<0>{});
-        else if (TY > 1 && rw == 1) phase2(std::true_type{}, RowOf<(TY > 1 ? 1 : 0)>{});
-        else if (TY > 2 && rw == 2) phase2(std::true_type{}, RowOf<(TY > 2 ? 2 : 0)>{});
-        else if (TY > 3 && rw == 3) phase2(std::true_type{}, RowOf<(TY > 3 ? 3 : 0)>{});
-        else if (TY > 4 && rw == 4) phase2(std::true_type{}, RowOf<(TY > 4 ? 4 : 0)>{});
-        else if (TY > 5) phase2(std::true_type{}, RowOf<(TY > 5 ? 5 : 0)>{});
+        if (rw == 0) phase2(std::true_type{}, RowOf<0>{}, no_ghost);
+        else if (TY > 1 && rw == 1) phase2(std::true_type{}, RowOf<(TY > 1 ? 1 : 0)>{}, no_ghost);
+        else if (TY > 2 && rw == 2) phase2(std::true_type{}, RowOf<(TY > 2 ? 2 : 0)>{}, no_ghost);
+        else if (TY > 3 && rw == 3) phase2(std::true_type{}, RowOf<(TY > 3 ? 3 : 0)>{}, no_ghost);
+        else if (TY > 4 && rw == 4) phase2(std::true_type{}, RowOf<(TY > 4 ? 4 : 0)>{}, no_ghost);
+        else if (TY > 5) phase2(std::true_type{}, RowOf<(TY > 5 ? 5 : 0)>{}, no_ghost);
     } else if (lanes_form_row) {
-        phase2(std::true_type{}, RowOf<-1>{});
+        phase2(std::true_type{}, RowOf<-1>{}, no_ghost);
     } else {
-        phase2(std::false_type{}, RowOf<-1>{});
+        phase2(std::false_type{}, RowOf<-1>{}, no_ghost);
     }
 }
 
@@ -709,8 +732,8 @@ hipError_t launch_tiles(const Consts* dc, int nx, int ny, const double* fin, dou
         hipLaunchKernelGGL((k_step_sf<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
     else if constexpr (MODE == 3)
-        hipLaunchKernelGGL((k_step_sh<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND>), dim3(per * kXcds), dim3(TX * TY), 0,
-                           st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl);
+        hipLaunchKernelGGL((k_step_sh<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND, GHOST>), dim3(per * kXcds),
+                           dim3(TX * TY), 0, st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl, gb);
     else
         hipLaunchKernelGGL((k_step<TX, TY, AMOD, CHEM, GEXP, SRT, BLEND, GHOST>), dim3(per * kXcds), dim3(TX * TY), 0,
                            st, dc, fin, fout, lin, lout, uin, uout, gx, ntiles, vertical, bl, gb);
@@ -754,7 +777,7 @@ hipError_t launch_shape(const Consts* dc, int flags, int nx, int ny, const doubl
 const int kStepVariants[][3] = {{64, 4, 1}, {32, 8, 1}, {128, 2, 1}, {256, 2, 0}, {256, 1, 0}, {64, 4, 0},
                                 {64, 4, 2}, {32, 8, 2}, {128, 2, 2}, {256, 1, 2}, {64, 4, 3}, {128, 2, 3}};
 const int kNumStepVariants = sizeof(kStepVariants) / sizeof(kStepVariants[0]);
-const int kWallTile[2] = {64, 4};   // the one shape compiled with the wall (ghost-layer) stencil
+const int kWallTile[3] = {64, 4, 3};   // the one shape compiled with the wall (ghost-layer) stencil
 
 // The reaction is always compiled in (flag 2): without a reaction the wave-uniform test on
 // the Cochran increment skips it at run time, and that kernel runs an inert step faster
@@ -771,11 +794,11 @@ hipError_t launch_step(const Consts* dc, int variant, int flags, int nx, int ny,
                        double* fout, const double* lin, double* lout, const double* uin, double* uout,
                        int vertical, hipStream_t st, const Blend* bl, const double* gb) {
     if (gb) {
-        // wall sides: the 64 x 4 direct shape (kWallTile), whatever the tuned one
-        if (bl) return launch_flags<64, 4, 0, true, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout,
+        // wall sides: the 64 x 4 shared-centre shape (kWallTile), whatever the tuned one
+        if (bl) return launch_flags<64, 4, 3, true, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout,
                                                                vertical, st, *bl, gb);
         const Blend none{nullptr, nullptr, 0.0, 1.0};
-        return launch_flags<64, 4, 0, false, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical,
+        return launch_flags<64, 4, 3, false, true>(dc, flags, nx, ny, fin, fout, lin, lout, uin, uout, vertical,
                                                         st, none, gb);
     }
     switch (variant) {
