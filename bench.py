@@ -84,6 +84,13 @@ def measured_traffic(tile):
     return None
 
 
+def _finite_or_none(v):
+    """A float for the JSON line, None where it is not finite (the margin of a state
+    without unburnt cells is +inf)."""
+    import math
+    return v if math.isfinite(v) else None
+
+
 def time_steps(sim, steps, warmup):
     import torch
     sim.step(warmup)
@@ -298,7 +305,8 @@ def bench_small_configs(ns_per_cell_plain, oracle_rates=True):
         gbs = BYTES_PER_CELL * cells * w.steps / (ms * 1e-3) / 1e9
         r = {"cells": cells, "steps": w.steps, "run_ms": round(ms, 3), "ms_per_step": round(ms / w.steps, 5),
              "mlups": round(cells * w.steps / (ms * 1e-3) / 1e6, 2), "algorithmic_gbs": round(gbs, 1),
-             "hbm_frac": round(gbs / HBM_PEAK_GBS, 5), "launch": list(launch), "finite": bool(s.check())}
+             "hbm_frac": round(gbs / HBM_PEAK_GBS, 5), "launch": list(launch), "finite": bool(s.check()),
+             "ignition_margin_after_run": _finite_or_none(s.ignition_margin())}
         s.close()
         if oracle_rates:
             r1, d1 = _oracle_rate(w, osteps, 1)
@@ -407,6 +415,7 @@ def main():
         launch = sim.autotune()                 # launch shape: tile, LDS staging, tile order
     ms = time_steps(sim, args.steps, args.warmup)
     ok = sim.check()
+    margin = _finite_or_none(sim.ignition_margin())
     del sim
     torch.cuda.empty_cache()
     value = cells / (ms * 1e-3) / 1e6
@@ -483,7 +492,7 @@ def main():
                    "rates": "R_1..R_24 = %g (all equal)" % w.R[4] if len(set(w.R)) == 1 else list(w.R),
                    "omega1_omega2": [w.omega1, w.omega2],
                    "launch": {"tile": [launch[0], launch[1]], "lds": launch[2], "column_bands": launch[3]},
-                   "state_finite_after_run": bool(ok)},
+                   "state_finite_after_run": bool(ok), "ignition_margin_after_run": margin},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": step_kernel_name(launch[:3]),

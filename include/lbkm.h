@@ -147,6 +147,14 @@ lbkm_status lbkm_reduce(lbkm_ctx* ctx, double out[8]);
  * lambda, rho <= 0 or T <= 0; LBKM_OK otherwise. */
 lbkm_status lbkm_check(lbkm_ctx* ctx);
 
+/* Ignition margin of the current state (synchronises): *margin (host) receives the
+ * minimum of |T - T_ig| over the cells with lambda < 1, +infinity when there is none.
+ * The ignition test T > T_ig (Sec. II, the rate law) is the one discontinuity of the
+ * step; a margin far above rounding shows that no cell sits on it, so implementations
+ * that round differently still take the same branch everywhere.  EINVAL for a NULL
+ * margin; ESTATE before buffers, parameters and fields are set. */
+lbkm_status lbkm_ignition_margin(lbkm_ctx* ctx, double* margin);
+
 /* Copy the current state out to / in from caller device buffers f[24][ny][nx]
  * and lam[ny][nx] (dense, asynchronous).  set_state marks the fields as set. */
 lbkm_status lbkm_get_state(lbkm_ctx* ctx, double* f, double* lam);

@@ -68,6 +68,9 @@ the mathematics, never against the oracle itself):
                         wave equal the Chapman-Enskog stresses for I = 1, 3, 4;
                         conservation on periodic grids
   tne, reductions       readout identities (Sec. VI)
+  ignition_margin       equals min |T - T_ig| of the temperature field a state was
+                        initialised from (over the cells with lambda < 1), +inf
+                        when every cell has burnt
   (reverse-mode AD)     the gradient of a run agrees with central differences of
                         the oracle's forward run
   physics.*             the paper's CJ numbers (tests/golden/cj_state.txt); Rankine-
@@ -80,11 +83,12 @@ printed; a project choice of the workloads).
 from .dvm import DVM, velocity_set, moment_matrix, inverse_moment_matrix
 from .model import Params, Tables, make_tables, equilibrium_moments, macroscopic, \
     modification_terms, cochran_increment, chemical_term, nnd_derivative, \
-    collision, collision_srt, step, run, init_f, moments, tne, reductions, wall_layers, padded
+    collision, collision_srt, step, run, init_f, moments, tne, reductions, ignition_margin, wall_layers, \
+    padded
 
 __all__ = [
     "DVM", "velocity_set", "moment_matrix", "inverse_moment_matrix",
     "Params", "Tables", "make_tables", "equilibrium_moments", "macroscopic",
     "modification_terms", "cochran_increment", "chemical_term", "nnd_derivative",
-    "collision", "step", "run", "init_f", "moments", "tne", "reductions",
+    "collision", "step", "run", "init_f", "moments", "tne", "reductions", "ignition_margin",
 ]

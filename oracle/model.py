@@ -476,6 +476,17 @@ def tne(f, P: Params, tab: Tables):
     return delta, torch.sqrt((delta * delta).sum(0))
 
 
+def ignition_margin(f, lam, P: Params, tab: Tables):
+    """min |T - T_ig| over the cells with lambda < 1 (+inf if none): the distance of the
+    state from the one discontinuity of the step, the ignition test T > T_ig of the rate
+    law (Sec. II)."""
+    _, _, _, T = macroscopic(moment_transform(f, tab), P.I)
+    live = lam < 1.0
+    if not bool(live.any()):
+        return float("inf")
+    return float((T[live] - P.T_ig).abs().min())
+
+
 def reductions(f, lam, P: Params, tab: Tables):
     """[sum rho, sum rho u_x, sum rho u_y, sum E_tot, sum_cells sum_k Delta_k^2,
     (dx / Ny) sum |Delta_5|, min lambda, max lambda]; E_tot = f_hat_4 / 2 is the total

@@ -438,6 +438,21 @@ lbkm_status lbkm_reduce(lbkm_ctx* ctx, double out[8]) {
     return LBKM_OK;
 }
 
+lbkm_status lbkm_ignition_margin(lbkm_ctx* ctx, double* margin) {
+    lbkm_status st = ready(ctx, true);
+    if (st != LBKM_OK) return st;
+    if (!margin) return fail(ctx, LBKM_EINVAL, "NULL output");
+    const int64_t cells = (int64_t)ctx->grid.nx * ctx->grid.ny;
+    int nb = (int)((cells + 255) / 256);
+    if (nb > kReduceBlocks) nb = kReduceBlocks;
+    hipError_t e = launch_margin(ctx->d, ctx->f[ctx->cur], ctx->lam[ctx->cur], ctx->partials, nb, ctx->out8,
+                                 ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(margin, ctx->out8, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "ignition margin");
+    return LBKM_OK;
+}
+
 lbkm_status lbkm_check(lbkm_ctx* ctx) {
     lbkm_status st = ready(ctx, true);
     if (st != LBKM_OK) return st;

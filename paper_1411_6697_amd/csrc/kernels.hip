@@ -169,6 +169,54 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
         for (int k = 0; k < 8; ++k) out[k] = v[k];
 }
 
+// ignition margin: per-work-group minima of |T - T_ig| over the cells with lambda < 1
+__global__ __launch_bounds__(256) void k_margin_partial(const Consts* __restrict__ c,
+                                                        const double* __restrict__ f,
+                                                        const double* __restrict__ lam,
+                                                        double* __restrict__ partials) {
+    __shared__ double sh[4];
+    const int64_t cells = (int64_t)c->nx * c->ny;
+    double v = INFINITY;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cells;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(q / c->nx), x = (int)(q % c->nx);
+        const int64_t at = (int64_t)y * c->pitch + x;
+        if (!(lam[at] < 1.0)) continue;
+        double fv[NV];
+        load_cell(f, c->plane, at, fv);
+        Blocks s, h;
+        to_combos(fv, s);
+        forward(c, s, h);
+        const Macro m = macro_of(h, c->DI);
+        v = fmin(v, fabs(m.T - c->Tig));
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmin(v, sh[w]);
+        partials[blockIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_min_final(const double* __restrict__ partials, int n,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[4];
+    double v = INFINITY;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) v = fmin(v, partials[b]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmin(v, sh[w]);
+        out[0] = v;
+    }
+}
+
 // health check: NaN/Inf anywhere in f or lambda, rho <= 0 or T <= 0
 __global__ __launch_bounds__(256) void k_check(const Consts* __restrict__ c, const double* __restrict__ f,
                                                const double* __restrict__ lam, int* flag) {
@@ -339,6 +387,13 @@ hipError_t launch_moments(const Consts* dc, int nx, int ny, const double* f, con
 hipError_t launch_tne(const Consts* dc, int nx, int ny, const double* f, double* delta, double* dist,
                       hipStream_t st) {
     hipLaunchKernelGGL(k_tne, row_grid(nx, ny), dim3(256), 0, st, dc, f, delta, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_margin(const Consts* dc, const double* f, const double* lam, double* partials,
+                         int nblocks, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_margin_partial, dim3(nblocks), dim3(256), 0, st, dc, f, lam, partials);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, st, partials, nblocks, out);
     return hipGetLastError();
 }
 

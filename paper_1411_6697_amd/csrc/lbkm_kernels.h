@@ -47,6 +47,9 @@ hipError_t launch_reduce(const Consts* dc, const double* f, const double* lam, d
                          int nblocks, double* out, hipStream_t st);
 hipError_t launch_check(const Consts* dc, int nx, int ny, const double* f, const double* lam, int* flag,
                         hipStream_t st);
+// min over cells with lambda < 1 of |T - T_ig| into out[0] (partials: nblocks doubles)
+hipError_t launch_margin(const Consts* dc, const double* f, const double* lam, double* partials,
+                         int nblocks, double* out, hipStream_t st);
 hipError_t launch_copy_state(const Consts* dc, int nx, int ny, const double* src, double* dst, int planes,
                              int to_dense, hipStream_t st);
 

@@ -60,6 +60,7 @@ SIGNATURES = {
     "lbkm_get_tne": [_P, _P, _P],
     "lbkm_reduce": [_P, _D],
     "lbkm_check": [_P],
+    "lbkm_ignition_margin": [_P, _D],
     "lbkm_get_state": [_P, _P, _P],
     "lbkm_set_state": [_P, _P, _P],
     "lbkm_get_step_count": [_P, ctypes.POINTER(ctypes.c_int64)],
@@ -211,6 +212,12 @@ class Sim:
         out = (ctypes.c_double * 8)()
         self._call("lbkm_reduce", out)
         return np.array(out[:], dtype=np.float64)
+
+    def ignition_margin(self) -> float:
+        """min |T - T_ig| over the cells with lambda < 1 (inf when there is none)."""
+        out = ctypes.c_double()
+        self._call("lbkm_ignition_margin", ctypes.byref(out))
+        return float(out.value)
 
     def check(self) -> bool:
         st = self.lib.lbkm_check(self.h)

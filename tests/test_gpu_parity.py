@@ -430,6 +430,20 @@ def test_tne_and_reductions_match_oracle():
     assert np.allclose(r[4:6], ro[4:6], rtol=1e-8)
     assert r[6] == ro[6] or abs(r[6] - ro[6]) < 1e-12
     assert abs(r[7] - ro[7]) < 1e-12
+    # the ignition margin: min |T - T_ig| over unburnt cells, a difference of temperatures
+    # of order one, so the two agree to rounding of T
+    mg, mo = s.ignition_margin(), oracle.ignition_margin(f, lam, P, tab)
+    print("ignition margin", mg, mo, flush=True)
+    assert math.isfinite(mo) and abs(mg - mo) <= 1e-12
+
+
+def test_ignition_margin_of_a_burnt_state_is_infinite():
+    """Every cell burnt (lambda = 1): no cell can ignite, the margin is +inf."""
+    w = W.sod(nx=64, steps=0)
+    F = {k: np.asarray(v) for k, v in w.fields().items()}
+    F["lam"] = np.ones_like(F["lam"])
+    s, _ = _gpu(w, 0, fields=F)
+    assert s.ignition_margin() == math.inf
 
 
 def test_check_flags_nonfinite_and_nonpositive_states():

@@ -780,6 +780,32 @@ def test_tne_readout_identities():
     assert torch.isclose(r[4], (delta ** 2).sum())
 
 
+def test_ignition_margin_is_the_distance_of_the_initial_temperature_from_T_ig():
+    """On a state initialised from a known temperature field, the ignition margin equals
+    min |T - T_ig| of that field over the cells with lambda < 1 (init_f recovers T to
+    rounding); burnt cells (lambda = 1) do not count, and a fully burnt state has none."""
+    w = W.detonation(nx=40, ny=3, steps=1)
+    P, tab = oracle_init(w)[:2]
+    g = np.random.default_rng(5)
+    T = torch.from_numpy(0.9 + 0.5 * g.random((3, 40)))
+    rho = torch.from_numpy(1.0 + 0.2 * g.random((3, 40)))
+    ux = torch.from_numpy(0.1 * g.standard_normal((3, 40)))
+    uy = torch.from_numpy(0.1 * g.standard_normal((3, 40)))
+    lam = torch.from_numpy(np.where(g.random((3, 40)) < 0.3, 1.0, 0.5))
+    f = oracle.init_f(rho, ux, uy, T, P, tab)
+    live = lam < 1.0
+    expect = float((T[live] - P.T_ig).abs().min())
+    assert abs(oracle.ignition_margin(f, lam, P, tab) - expect) <= 1e-13
+    # the closest cell burnt: the margin moves to the next closest live cell
+    k = int(torch.argmin(torch.where(live, (T - P.T_ig).abs(), torch.full_like(T, np.inf))))
+    lam2 = lam.clone().reshape(-1)
+    lam2[k] = 1.0
+    lam2 = lam2.reshape(3, 40)
+    live2 = lam2 < 1.0
+    assert abs(oracle.ignition_margin(f, lam2, P, tab) - float((T[live2] - P.T_ig).abs().min())) <= 1e-13
+    assert oracle.ignition_margin(f, torch.ones_like(lam), P, tab) == float("inf")
+
+
 # ---------------------------------------------------------------------------
 # Physics references and whole-run validation
 # ---------------------------------------------------------------------------
