@@ -647,8 +647,8 @@ __global__ __launch_bounds__(kAdjThreads, 2) void k_adj_stream(const Consts* __r
             double acc = 0.0, a_c = 0.0;          // a_c: a^{n+1} of this cell (offset 0 of a stencil)
             if (DUX[d] != 0) {
                 if (XL) {
-                    const XNeighbours nf = x_neighbours(cur.fx[2], cur.hf, lane);
-                    const XNeighbours na = x_neighbours(cur.ax[2], cur.ha, lane);
+                    const XNeighbours nf = x_neighbours(cur.fx[2], cur.hf);
+                    const XNeighbours na = x_neighbours(cur.ax[2], cur.ha);
                     cur.fx[0] = nf.m2;
                     cur.fx[1] = nf.m1;
                     cur.fx[3] = nf.p1;

@@ -221,7 +221,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
             const double f0 = stash[i * kBatchThreads];
             double a = f0;
             if (DUX[d] != 0) {
-                const XNeighbours n = x_neighbours(f0, hcur, lane);
+                const XNeighbours n = x_neighbours(f0, hcur);
                 if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
                 if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
             }
@@ -234,7 +234,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
             st(Uo, 0u, oc, va.jx / va.r);
             st(Uo, opaque(Uo.plane_bytes), oc, va.jy / va.r);
         }
-        const XNeighbours n = x_neighbours(lam, hlam, lane);
+        const XNeighbours n = x_neighbours(lam, hlam);
         const double dlx = nnd_upwind(m.ux > 0.0, n.m2, n.m1, lam, n.p1, n.p2);
         st(Lo, 0u, oc, lam + dlam - dt * (m.ux * (dlx * idx_)));
     };

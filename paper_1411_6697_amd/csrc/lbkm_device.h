@@ -242,37 +242,37 @@ __device__ __forceinline__ double nnd_upwind(bool pos, double fm2, double fm1, d
 }
 
 // Lane moves of a double across the wave (DPP): lane i receives lane i-1's value
-// (from_left) or lane i+1's (from_right); the end lane keeps 0 and is patched by the caller.
-__device__ __forceinline__ double from_left(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);   // wave_shr:1
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
+// (from_left) or lane i+1's (from_right).  The end lane, which has no source lane, is not
+// written and keeps `edge`.
+__device__ __forceinline__ double from_left(double v, double edge) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);   // 0x138: wave_shr:1
 }
-__device__ __forceinline__ double from_right(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);   // wave_shl:1
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
+__device__ __forceinline__ double from_right(double v, double edge) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);   // 0x130: wave_shl:1
 }
 
-// The x-neighbours of one plane for a wave that holds 64 consecutive cells of a row, from
-// the centre values of the neighbouring lanes.  h is the plane's halo: lanes 0-31 hold the
-// value at x0-1 (lane 0: x0-2), lanes 32-63 the value at x0+64 (lane 63: x0+65), x0 being
-// the wave's first cell, each index under the boundary rule.
+// The x-neighbours at offsets -2, -1, +1, +2 of a row of 64 cells held one per lane
+// (centre value f0), with h the lane's halo value: x0-2 on lane 0, x0-1 on lanes 1..31,
+// x0+64 on lanes 32..62, x0+65 on lane 63 (x0 the row's first cell, positions under the
+// boundary rule).  Each neighbour is one lane move whose end lane keeps the halo value it
+// needs: -1 on lane 0 is x0-1 (lane 1's halo), -2 on lane 1 is lane 0's -1, -2 on lane 0
+// is its own halo, and the same mirrored at lane 63.
 struct XNeighbours {
     double m2, m1, p1, p2;
 };
-__device__ __forceinline__ XNeighbours x_neighbours(double f0, double h, int lane) {
-    const double l1 = from_left(f0), r1 = from_right(f0);
-    const double l2 = from_left(l1), r2 = from_right(r1);
+__device__ __forceinline__ XNeighbours x_neighbours(double f0, double h) {
     // every lane takes part in the halo load (left to itself the compiler would load it on
     // the end lanes only, behind a branch and a wait per plane)
     asm("" : "+v"(h));
-    const double hl = from_right(h), hr = from_left(h);
     XNeighbours n;
-    n.m2 = lane < 2 ? h : l2;
-    n.m1 = lane == 0 ? hl : l1;     // lane 0: x0-1, held by lane 1
-    n.p1 = lane == 63 ? hr : r1;    // lane 63: x0+64, held by lane 62
-    n.p2 = lane >= 62 ? h : r2;
+    n.m1 = from_left(f0, from_right(h, 0.0));
+    n.p1 = from_right(f0, from_left(h, 0.0));
+    n.m2 = from_left(n.m1, h);
+    n.p2 = from_right(n.p1, h);
     return n;
 }
 

@@ -467,7 +467,7 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
                 const double f0 = f[8 * g + d];
                 double a = f0;
                 if (XL && DUX[d] != 0) {
-                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo), lane);
+                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo));
                     if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
                     if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
                 } else {
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3)
                 auto at = [&](uint32_t off, int k) { return sld<GH>(F, so, off, Gb, sg, gh, k); };
                 double a = f0;
                 if (XL && DUX[d] != 0) {
-                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo), lane);
+                    const XNeighbours n = x_neighbours(f0, ld(F, so, halo));
                     if (DUX[d] > 0) a = fma(-wx, nnd_pos(n.m2, n.m1, f0, n.p1), a);
                     if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
                 } else {
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3)
         auto lat = [&](uint32_t off, int k) { return sld<GH>(L, 0u, off, Gb, sl, gh, k); };
         double dlx;
         if (XL) {
-            const XNeighbours n = x_neighbours(lam, ld(L, 0u, halo), lane);
+            const XNeighbours n = x_neighbours(lam, ld(L, 0u, halo));
             dlx = nnd_upwind(m.ux > 0.0, n.m2, n.m1, lam, n.p1, n.p2);
         } else {
             dlx = nnd_upwind(m.ux > 0.0, lat(s.xm2, 0), lat(s.xm1, 1), lam, lat(s.xp1, 2), lat(s.xp2, 3));
