@@ -56,9 +56,10 @@ def step_kernel_name(tile) -> str:
 
 
 def measured_traffic(tile):
-    """HBM bytes per launch of the step kernel at launch `tile` = (tile_x, tile_y, mode),
-    from the committed rocprofv3 counter summary, if that was taken on the current kernel
-    source and holds that launch shape; else None."""
+    """HBM bytes per launch of the step kernel at launch `tile` = (tile_x, tile_y, mode) or
+    (tile_x, tile_y, mode, column_bands), from the committed rocprofv3 counter summary, if
+    that was taken on the current kernel source and holds that launch shape (and, when
+    given, that tile order); else None."""
     if not os.path.exists(PMC_FILE):
         return None
     src_hash, per_kernel = None, {}
@@ -77,6 +78,8 @@ def measured_traffic(tile):
     want = STEP_KERNELS[int(tile[2])] + f"<{int(tile[0])},{int(tile[1])},"
     for name, kv in per_kernel.items():
         if name.startswith(want):
+            if len(tile) > 3 and kv.get("launch", "").rpartition(":")[2] != str(int(tile[3])):
+                return None
             try:
                 return float(kv["hbm_bytes_per_launch"])
             except (KeyError, ValueError):
@@ -472,7 +475,7 @@ def main():
 
     achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
     ceiling = copy_ceiling_gbs()
-    traffic = measured_traffic(launch[:3])
+    traffic = measured_traffic(launch[:4])
     out = {
         "metric": "MLUPS (cell updates/s) FP64 at 2048\u00b2; batched & adjoint vs plain step time",
         "value": round(value, 2),

@@ -224,9 +224,12 @@ lbkm_status lbkm_set_boundary(lbkm_ctx* ctx, int32_t side, int32_t type, const d
 lbkm_status lbkm_set_time_scheme(lbkm_ctx* ctx, int32_t order);
 
 /* Autotuner of the launch shape: times every compiled (tile, lds) shape in both tile
- * orders for a few steps from the current state, keeps the fastest, and restores the
- * state and the step count (the trial steps run on the bound buffers; a temporary copy
- * of the state is allocated).  With wall sides there is one shape (64 x 4, shared centres) and
+ * orders for a few steps from the current state (two passes, the better trial of each
+ * candidate counts), keeps the fastest, and restores the state and the step count (the
+ * trial steps run on the bound buffers; a temporary copy of the state is allocated).
+ * Row bands (vertical = 0) must be faster than column bands by more than 2 % to be kept:
+ * they give each XCD a band of rows, so work that later gathers in some rows (a layer
+ * that ignites) would load some XCDs more than others, which the trial cannot see.  With wall sides there is one shape (64 x 4, shared centres) and
  * only the two tile orders are timed.  Needs parameters and fields.  choice (host, 4 ints, may be NULL)
  * receives tile_x, tile_y, lds, vertical.  Synchronous. */
 lbkm_status lbkm_autotune(lbkm_ctx* ctx, int32_t* choice);

@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the one-GPU refusal and the rule that a committed
-counter summary is used only for the kernel source and launch shape it was taken on."""
+counter summary is used only for the kernel source, launch shape and tile order it was
+taken on."""
 
 import json
 import os
@@ -46,6 +47,23 @@ def test_committed_traffic_is_read_only_for_its_own_source_and_launch():
     for other in ((512, 1, 0), (16, 16, 2), (64, 4, 1)):
         if other not in tiles:
             assert bench.measured_traffic(other) is None
+
+
+def test_committed_traffic_is_read_only_for_its_own_tile_order():
+    orders = {}
+    with open(bench.PMC_FILE) as fh:
+        for line in fh:
+            m = re.match(r"kernel k_step(_lds|_sf|_sh)?<(\d+),(\d+),.* launch \S+:(\d)", line)
+            if m:
+                mode = {None: 0, "_lds": 1, "_sf": 2, "_sh": 3}[m.group(1)]
+                orders[(int(m.group(2)), int(m.group(3)), mode)] = int(m.group(4))
+    assert orders, "the counter summary names no tile order"
+    tiles = _profiled_tiles()
+    for tile, order in orders.items():
+        if bench.measured_traffic(tile) is None:
+            continue                       # the summary predates the current kernel source
+        assert bench.measured_traffic(tile + (order,)) == tiles[tile]
+        assert bench.measured_traffic(tile + (1 - order,)) is None
 
 
 def test_traffic_is_ignored_when_the_kernel_source_changes(monkeypatch):
