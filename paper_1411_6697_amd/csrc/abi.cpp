@@ -113,6 +113,10 @@ lbkm_status build_tables(lbkm_ctx* ctx, const lbkm_grid* g) {
     c.inv_dy = 1.0 / g->dy;
     c.half_inv_dx = 1.0 / (2.0 * g->dx);
     c.half_inv_dy = 1.0 / (2.0 * g->dy);
+    for (int k = 0; k < 3; ++k) {
+        c.cx[k] = c.dt * c.vg[k] * c.inv_dx;
+        c.cy[k] = c.dt * c.vg[k] * c.inv_dy;
+    }
     c.nx = g->nx;
     c.ny = g->ny;
     c.bc_x = g->bc_x;

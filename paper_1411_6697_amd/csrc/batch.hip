@@ -90,21 +90,11 @@ __device__ __forceinline__ bool wait_counter(const uint32_t* flags, int nb, int 
     return false;
 }
 
-// Constants of the streaming part, read once before the step loop: inside it every
-// step's device-scope fence counts as a write to all memory, after which the compiler
-// reads the constants block with vector loads, each one a wait that also drains the
-// stencil loads in flight.
-struct StreamConsts {
-    double dt, inv_dx, half_inv_dx;
-    double vg[3];                               // speeds of the three groups
-    double wx[3];                               // Courant numbers dt v_g / dx of the groups
-};
-
 // one step of one cell of a 1D instance (x-derivatives only; y-differences are zero).
 // [lo, hi] is the instance, cells below `end` are updated in this pass of the work-group,
 // stash holds this thread's 24 LDS slots ([plane][kBatchThreads]).
 template <bool AMOD, bool CHEM, bool GEXP>
-__device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const StreamConsts& k,
+__device__ __forceinline__ void cell_1d(const Consts* __restrict__ c,
                                         const BatchInst* __restrict__ I, int lo, int hi, int end, int j,
                                         const Soa& F, const Soa& G, const Soa& L, const Soa& Lo, const Soa& Ui,
                                         const Soa& Uo, double* stash) {
@@ -126,8 +116,8 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
         if (AMOD && ro(I->amod)) {
             // the neighbours' velocities, written by the previous step (or k_velocity)
             const uint32_t up = opaque(Ui.plane_bytes);
-            gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * k.half_inv_dx;
-            gyx = (ld(Ui, up, op1) - ld(Ui, up, om1)) * k.half_inv_dx;
+            gxx = (ld(Ui, 0u, op1) - ld(Ui, 0u, om1)) * ro(c->half_inv_dx);
+            gyx = (ld(Ui, up, op1) - ld(Ui, up, om1)) * ro(c->half_inv_dx);
         }
         double f[NV];
         load_cell(F, oc, f);
@@ -145,7 +135,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
         local_source<CHEM, GEXP>(c, c->mat, lam, A8, A9, m, h, src, dlam, I->R);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const double dt = k.dt, idx_ = k.inv_dx;
+    const double dt = ro(c->dt), idx_ = ro(c->inv_dx);
     const uint32_t pb = opaque(F.plane_bytes);
     // The input and output buffers trade places from step to step, so the compiler cannot
     // tell that a store of plane i leaves plane i+1's stencil unchanged, and would issue
@@ -187,13 +177,13 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
             }
             __builtin_amdgcn_sched_barrier(0);
             const int g = i / 8, d = i % 8;
-            const double wx = k.wx[g];                // Courant number of the group
+            const double wx = ro(c->cx[g]);           // Courant number of the group
             const double f0 = cur.v[2];
             double a = f0;
             if (DUX[d] > 0) a = fma(-wx, nnd_pos(cur.v[0], cur.v[1], f0, cur.v[3]), a);
             if (DUX[d] < 0) a = fma(wx, nnd_neg(cur.v[1], f0, cur.v[3], cur.v[4]), a);
             double out = fma(dt, src[i], a);
-            if (AMOD) vel_add(va, k.vg[g], d, out);
+            if (AMOD) vel_add(va, c, g, d, out);
             st(G, (uint32_t)i * pb, oc, out);
             cur = nxt;
         }
@@ -217,7 +207,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
             }
             __builtin_amdgcn_sched_barrier(0);
             const int g = i / 8, d = i % 8;
-            const double wx = k.wx[g];
+            const double wx = ro(c->cx[g]);
             const double f0 = stash[i * kBatchThreads];
             double a = f0;
             if (DUX[d] != 0) {
@@ -226,7 +216,7 @@ __device__ __forceinline__ void cell_1d(const Consts* __restrict__ c, const Stre
                 if (DUX[d] < 0) a = fma(wx, nnd_neg(n.m1, f0, n.p1, n.p2), a);
             }
             double out = fma(dt, src[i], a);
-            if (AMOD) vel_add(va, k.vg[g], d, out);
+            if (AMOD) vel_add(va, c, g, d, out);
             st(G, (uint32_t)i * pb, oc, out);
             hcur = hnxt;
         }
@@ -262,15 +252,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
     __shared__ double stash[NV * kBatchThreads];       // each thread's centre values (own slots)
     // the descriptors are swapped after every step (selecting them by step parity inside
     // the loop would turn them into per-lane values)
-    StreamConsts k;
-    k.dt = c->dt;
-    k.inv_dx = c->inv_dx;
-    k.half_inv_dx = c->half_inv_dx;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        k.vg[g] = c->vg[g];
-        k.wx[g] = c->dt * c->vg[g] * c->inv_dx;
-    }
     Soa F = soa(parity ? f1 : f0, c->plane), G = soa(parity ? f0 : f1, c->plane);
     Soa L = soa(parity ? l1 : l0, 0), Lo = soa(parity ? l0 : l1, 0);
     Soa Ui = soa(parity ? u1 : u0, c->plane), Uo = soa(parity ? u0 : u1, c->plane);
@@ -294,7 +275,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const Consts* __restric
             for (int base = S.begin; base < S.end; base += kBatchThreads) {
                 const int j = base + (int)threadIdx.x;
                 if (j < S.end)
-                    cell_1d<AMOD, CHEM, GEXP>(c, k, I, S.lo, S.hi, S.end, j, F, G, L, Lo, Ui, Uo,
+                    cell_1d<AMOD, CHEM, GEXP>(c, I, S.lo, S.hi, S.end, j, F, G, L, Lo, Ui, Uo,
                                               stash + threadIdx.x);
             }
         }

@@ -37,6 +37,7 @@ struct Consts {
     double I, DI;                 // I and D + I
     double Q, w1, w2, pm, pn, Tig;
     double dt, inv_dx, inv_dy, half_inv_dx, half_inv_dy;
+    double cx[3], cy[3];          // Courant numbers (dt v_g) / dx and (dt v_g) / dy of the groups
     double a8c, a9c;              // (R_5 - R_8)/R_5 and (R_7 - R_9)/R_7
     double inv_tau;               // 1/tau of the single-relaxation-time form
     int32_t srt;                  // 1: single relaxation time (Eq. SRT) instead of MRT

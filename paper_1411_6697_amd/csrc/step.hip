@@ -236,8 +236,7 @@ __device__ __forceinline__ void step_cell(const Consts* __restrict__ c, const Ma
         VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const double v = ro(c->vg[g]);
-            const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
+            const double wx = ro(c->cx[g]), wy = ro(c->cy[g]);   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const uint32_t so = (uint32_t)(8 * g + d) * pb;
@@ -358,8 +357,7 @@ __device__ __forceinline__ void step_tile_lds(const Consts* __restrict__ c, cons
         const double f0 = q[0];
         if (i < NV) {
             const int g = i / 8, d = i % 8;
-            const double v = ro(c->vg[g]);
-            const double wx = dt * v * idx_, wy = dt * v * idy;
+            const double wx = ro(c->cx[g]), wy = ro(c->cy[g]);
             double a = f0;
             if (DUX[d] > 0) a = fma(-wx, nnd_pos(q[-2], q[-1], f0, q[1]), a);
             if (DUX[d] < 0) a = fma(wx, nnd_neg(q[-1], f0, q[1], q[2]), a);
@@ -459,8 +457,7 @@ __global__ __launch_bounds__(TX * TY, GEXP ? 2 : 3) void k_step_sf(const Consts*
         const uint32_t pb = opaque(F.plane_bytes);
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const double v = ro(c->vg[g]);
-            const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
+            const double wx = ro(c->cx[g]), wy = ro(c->cy[g]);   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const uint32_t so = (uint32_t)(8 * g + d) * pb;
@@ -610,8 +607,7 @@ __global__ __launch_bounds__(TX * TY, (GEXP || (GHOST && AMOD && CHEM)) ? 2 : 3)
         VelAcc va;                                  // velocity of the new state (for A_hat)
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
-            const double v = ro(c->vg[g]);
-            const double wx = dt * v * idx_, wy = dt * v * idy;   // Courant numbers of the group
+            const double wx = ro(c->cx[g]), wy = ro(c->cy[g]);   // Courant numbers of the group
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int i = 8 * g + d;
