@@ -176,8 +176,9 @@ def cpu_baseline(w, tile=1024, steps=8):
 
 
 def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
-    """Config of 128 ragged 1D detonations: autotune, then `steps` steps as graph replays of
-    `chunk` steps each (one persistent launch per replay)."""
+    """Config of 128 ragged 1D detonations: autotune (one launch per step, or the persistent
+    kernel at 1-8 work-groups per CU), then `steps` steps in calls of `chunk` steps each
+    (each call replays captured graphs)."""
     import torch
     from paper_1411_6697_amd import lbkm
     from paper_1411_6697_amd import workloads as W
@@ -240,8 +241,9 @@ def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
             "mlups": round(mlups, 2), "algorithmic_gbs": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "ns_per_cell_update": round(ms * 1e6 / b.total, 5),
             "vs_plain_step_time_per_cell": round(ms * 1e6 / b.total / ns_per_cell_plain, 3),
+            "launch_mode": "one launch per step" if per_cu == 0 else "persistent",
             "work_groups": wgs, "work_groups_per_cu": per_cu, "cells_per_work_group": cells_per_wg,
-            "graph_steps_per_replay": chunk,
+            "steps_per_call": chunk,
             "instances_physical_after_run": sum(ok),
             # instances whose temperature turned non-positive (the explicit scheme loses
             # stability near the driver when Pr approaches 5; the CPU oracle does the same)

@@ -289,11 +289,16 @@ lbkm_status lbkm_destroy(lbkm_ctx* ctx);
  * both ends, as the 1D problems of Sec. IV), sharing dx, dt, the velocity model
  * (Sec. III), gamma, Q and the rate law (Eq. for F, Sec. II), each with its own
  * R_1..R_24 (and Prandtl number).  The library owns the packed state: f[24][P] and
- * lambda[P], P = sum(nx) rounded up to 64, instances back to back.  One
- * lbkm_batch_step call replays a captured HIP graph holding one persistent kernel
- * launch that advances every instance n steps; neighbouring work-groups synchronise
- * through per-work-group step counters, every wait is bounded, and a wait that runs
- * out (work-groups not co-resident) sets a sticky error that lbkm_batch_status reports.
+ * lambda[P], P = sum(nx) rounded up to 64, instances back to back.  Two launch modes
+ * (lbkm_batch_set_launch, lbkm_batch_autotune), with bitwise identical results:
+ *  - persistent (the default, 2 work-groups per CU): one lbkm_batch_step call replays a
+ *    captured HIP graph holding one kernel launch that advances every instance n steps;
+ *    neighbouring work-groups synchronise through per-work-group step counters, every
+ *    wait is bounded, and a wait that runs out (work-groups not co-resident) sets a
+ *    sticky error that lbkm_batch_status reports;
+ *  - one launch per step: each step is one launch over all packed cells (64-cell waves,
+ *    each taking the instances it overlaps one at a time), replayed from captured graphs
+ *    of 64 launches and one of the remainder; no waits, no co-residency needed.
  * Calls on one context are ordered on its stream; two contexts may run concurrently.
  * Errors: LBKM_EINVAL for bad sizes or rates (checked per instance, message names it),
  * LBKM_ESTATE for calls out of order, LBKM_EDEVICE for HIP failures. */
@@ -314,16 +319,18 @@ lbkm_status lbkm_batch_set_params(lbkm_ctx* ctx, const double* S, const double* 
 lbkm_status lbkm_batch_init_fields(lbkm_ctx* ctx, const double* rho, const double* ux,
                                    const double* uy, const double* T, const double* lambda);
 
-/* Autotuner: times a few steps for each candidate number of work-groups per compute
- * unit (within the occupancy the device reports) and keeps the fastest.  The state
- * and the step count are saved and restored around the trials.  If never called,
- * two work-groups per compute unit are used.  *cells_per_wg (host, may be NULL)
- * receives the resulting cells per work-group.  Synchronous. */
+/* Autotuner: times a few steps of one launch per step and of the persistent kernel at
+ * each candidate number of work-groups per compute unit (within the occupancy the device
+ * reports) and keeps the fastest.  The state and the step count are saved and restored
+ * around the trials.  If never called, the persistent kernel at two work-groups per
+ * compute unit is used.  *cells_per_wg (host, may be NULL) receives the resulting cells
+ * per work-group (256 with one launch per step).  Synchronous. */
 lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg);
 
-/* Fix the launch shape instead of autotuning: wgs_per_cu work-groups per compute unit
- * (1..16).  LBKM_EINVAL if the kernel's occupancy does not allow that many (the shape
- * then falls back to the largest allowed).  Synchronous. */
+/* Fix the launch instead of autotuning: wgs_per_cu = 0 for one launch per step, 1..16 for
+ * the persistent kernel with that many work-groups per compute unit.  LBKM_EINVAL outside
+ * 0..16, or if the persistent kernel's occupancy does not allow that many (the shape then
+ * falls back to the largest allowed).  Synchronous. */
 lbkm_status lbkm_batch_set_launch(lbkm_ctx* ctx, int32_t wgs_per_cu);
 
 /* Advance every instance n steps, 0 <= n < 2^31 (asynchronous; replays a captured
@@ -339,7 +346,8 @@ lbkm_status lbkm_batch_total_cells(lbkm_ctx* ctx, int64_t* out);
 
 /* Synchronises the stream; LBKM_EDEVICE if a neighbour wait of any launch since the
  * last init ran out (the results are then invalid).  wgs, wgs_per_cu (host, may be
- * NULL) receive the current launch shape. */
+ * NULL) receive the current launch shape: work-groups per launch, and work-groups per
+ * compute unit (0 with one launch per step). */
 lbkm_status lbkm_batch_status(lbkm_ctx* ctx, int32_t* wgs, int32_t* wgs_per_cu);
 
 #ifdef __cplusplus

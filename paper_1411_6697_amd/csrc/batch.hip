@@ -35,7 +35,9 @@ namespace lbkm {
 struct BatchInst {
     double R[NV];
     double a8c, a9c;
-    int32_t amod, pad;
+    int32_t amod;
+    int32_t lo, hi;      // first and last packed cell of the instance
+    int32_t pad;
 };
 
 struct BatchSeg {
@@ -45,6 +47,7 @@ struct BatchSeg {
 };
 
 constexpr int kBatchThreads = 256;
+constexpr int kStepChunk = 64;        // launches per captured graph in the one-launch-per-step mode (even)
 constexpr int kSpinLimit = 1 << 20;   // neighbour waits are bounded (error, never a hang)
 
 struct BatchState {
@@ -60,8 +63,10 @@ struct BatchState {
     std::vector<BatchInst> h_inst;
     BatchInst* d_inst = nullptr;
     bool any_amod = false;
-    // launch decomposition
+    // launch decomposition (wgs_per_cu = 0: one launch per step instead of the persistent kernel)
     int wgs_per_cu = 2, nwg = 0, cus = 0;
+    int32_t* d_wave_inst = nullptr;    // per 64-cell wave: first and last instance it overlaps
+    int nwaves = 0;
     BatchSeg* d_seg = nullptr;
     int32_t* d_wg_seg = nullptr;
     int seg_cap = 0;
@@ -71,6 +76,9 @@ struct BatchState {
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int64_t exec_steps[2] = {-1, -1};
     int exec_nwg[2] = {-1, -1};
+    // one launch per step: [parity][a chunk of kStepChunk steps, the remainder]
+    hipGraphExec_t sexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int64_t sexec_steps[2][2] = {{-1, -1}, {-1, -1}};
     hipStream_t cap = nullptr;
 };
 
@@ -302,6 +310,59 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// One step of every instance, one packed cell per thread: the launch-per-step form of
+// k_batch (its launches replayed from a captured graph, the kernel boundary orders the
+// steps).  Wave w holds cells [64 w, 64 w + 64) and takes the instances that overlap it,
+// wave_inst[2 w] .. wave_inst[2 w + 1], one at a time, so that an instance's rates are
+// uniform over the wave; the cells are updated by the same code as in k_batch.
+template <bool AMOD, bool CHEM, bool GEXP>
+__global__ __launch_bounds__(kBatchThreads, 3) void k_batch_step(const Consts* __restrict__ c,
+                                                                 const BatchInst* __restrict__ inst,
+                                                                 const int32_t* __restrict__ wave_inst, int nwaves,
+                                                                 const double* f_in, double* f_out,
+                                                                 const double* l_in, double* l_out,
+                                                                 const double* u_in, double* u_out) {
+    __shared__ double stash[NV * kBatchThreads];       // each thread's centre values (own slots)
+    const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBatchThreads / 64) + (threadIdx.x >> 6)));
+    if (w >= nwaves) return;                           // whole waves
+    const int j = (int)(blockIdx.x * kBatchThreads + threadIdx.x);
+    const int64_t plane = ro(c->plane);
+    const Soa F = soa(f_in, plane), G = soa(f_out, plane);
+    const Soa L = soa(l_in, 0), Lo = soa(l_out, 0);
+    const Soa Ui = soa(u_in, plane), Uo = soa(u_out, plane);
+    const int k0 = ro(wave_inst[2 * w]), k1 = ro(wave_inst[2 * w + 1]);
+    for (int k = k0; k <= k1; ++k) {
+        const BatchInst* I = inst + k;
+        const int lo = ro(I->lo), hi = ro(I->hi);
+        if (j >= lo && j <= hi)
+            cell_1d<AMOD, CHEM, GEXP>(c, I, lo, hi, hi + 1, j, F, G, L, Lo, Ui, Uo, stash + threadIdx.x);
+    }
+}
+
+template <bool AMOD, bool CHEM, bool GEXP>
+void launch_batch_step_kernel(const Consts* dc, BatchState* b, int parity, hipStream_t st) {
+    const int q = parity & 1;
+    hipLaunchKernelGGL((k_batch_step<AMOD, CHEM, GEXP>), dim3((b->nwaves + kBatchThreads / 64 - 1) / (kBatchThreads / 64)),
+                       dim3(kBatchThreads), 0, st, dc, b->d_inst, b->d_wave_inst, b->nwaves, b->f[q], b->f[1 - q],
+                       b->lam[q], b->lam[1 - q], b->u[q], b->u[1 - q]);
+}
+
+// one step launch per step, `steps` of them, starting from buffer parity `parity`
+hipError_t launch_batch_steps(const Consts* dc, int flags, BatchState* b, int64_t steps, int parity, hipStream_t st) {
+    for (int64_t s = 0; s < steps; ++s) {
+        const int q = (int)((parity + s) & 1);
+        switch (flags) {
+            case 0: launch_batch_step_kernel<false, false, false>(dc, b, q, st); break;
+            case 1: launch_batch_step_kernel<true, false, false>(dc, b, q, st); break;
+            case 2: launch_batch_step_kernel<false, true, false>(dc, b, q, st); break;
+            case 3: launch_batch_step_kernel<true, true, false>(dc, b, q, st); break;
+            case 6: launch_batch_step_kernel<false, true, true>(dc, b, q, st); break;
+            default: launch_batch_step_kernel<true, true, true>(dc, b, q, st); break;
+        }
+    }
+    return hipGetLastError();
+}
+
 template <bool AMOD, bool CHEM, bool GEXP>
 void launch_batch_kernel(const Consts* dc, BatchState* b, int64_t steps, int parity, hipStream_t st) {
     hipLaunchKernelGGL((k_batch<AMOD, CHEM, GEXP>), dim3(b->nwg), dim3(kBatchThreads), 0, st, dc, b->d_inst,
@@ -345,12 +406,23 @@ void drop_graphs(BatchState* b) {
         b->exec[p] = nullptr;
         b->exec_steps[p] = -1;
         b->exec_nwg[p] = -1;
+        for (int r = 0; r < 2; ++r) {
+            if (b->sexec[p][r]) (void)hipGraphExecDestroy(b->sexec[p][r]);
+            b->sexec[p][r] = nullptr;
+            b->sexec_steps[p][r] = -1;
+        }
     }
 }
 
 // Cut the packed cells into nwg ranges and the ranges into per-instance segments.
 lbkm_status build_decomposition(lbkm_ctx* ctx, int wgs_per_cu) {
     BatchState* b = ctx->batch;
+    if (wgs_per_cu == 0) {                              // one launch per step: no ranges
+        b->nwg = (b->nwaves + kBatchThreads / 64 - 1) / (kBatchThreads / 64);
+        b->wgs_per_cu = 0;
+        drop_graphs(b);
+        return LBKM_OK;
+    }
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel_ptr(batch_flags(ctx->h, b)),
                                                                  kBatchThreads, 0);
@@ -406,6 +478,44 @@ lbkm_status batch_ready(lbkm_ctx* ctx, bool need_fields) {
     return LBKM_OK;
 }
 
+// One launch per step: graphs of kStepChunk launches (an even count, so the buffer parity
+// is the same after each replay) and one of the remainder, cached per parity and count.
+lbkm_status batch_run_steps(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
+    BatchState* b = ctx->batch;
+    const int p = b->cur;
+    hipError_t e = hipSuccess;
+    auto ready = [&](int r, int64_t count) -> hipError_t {
+        if (b->sexec[p][r] && b->sexec_steps[p][r] == count) return hipSuccess;
+        if (b->sexec[p][r]) (void)hipGraphExecDestroy(b->sexec[p][r]);
+        b->sexec[p][r] = nullptr;
+        b->sexec_steps[p][r] = -1;
+        hipError_t ce = hipSuccess;
+        if (!b->cap) ce = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        hipGraph_t g = nullptr;
+        if (ce == hipSuccess) ce = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+            hipError_t le = launch_batch_steps(ctx->d, batch_flags(ctx->h, b), b, count, p, b->cap);
+            ce = hipStreamEndCapture(b->cap, &g);
+            if (le != hipSuccess) ce = le;
+        }
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&b->sexec[p][r], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (ce == hipSuccess) b->sexec_steps[p][r] = count;
+        return ce;
+    };
+    const int64_t full = n / kStepChunk, rem = n % kStepChunk;
+    if (full > 0) {
+        e = ready(0, kStepChunk);
+        for (int64_t i = 0; i < full && e == hipSuccess; ++i) e = hipGraphLaunch(b->sexec[p][0], st);
+    }
+    if (rem > 0 && e == hipSuccess) {
+        e = ready(1, rem);
+        if (e == hipSuccess) e = hipGraphLaunch(b->sexec[p][1], st);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch step graphs");
+    return LBKM_OK;
+}
+
 // run `n` steps through the graph cache (one graph per buffer parity and step count)
 lbkm_status batch_run(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
     BatchState* b = ctx->batch;
@@ -415,6 +525,14 @@ lbkm_status batch_run(lbkm_ctx* ctx, int64_t n, hipStream_t st) {
     if (b->any_amod && !b->u_valid) {
         e = launch_velocity(ctx->d, (int)b->total, 1, b->f[p], b->u[p], st);
         if (e != hipSuccess) return hip_fail(ctx, e, "velocity kernel");
+    }
+    if (b->wgs_per_cu == 0) {
+        const lbkm_status rs = batch_run_steps(ctx, n, st);
+        if (rs != LBKM_OK) return rs;
+        b->cur = (int)((p + n) & 1);
+        b->u_valid = b->any_amod;
+        ctx->steps += n;
+        return LBKM_OK;
     }
     if (!b->exec[p] || b->exec_steps[p] != n || b->exec_nwg[p] != b->nwg) {
         if (b->exec[p]) (void)hipGraphExecDestroy(b->exec[p]);
@@ -458,6 +576,7 @@ void destroy_extras(lbkm_ctx* ctx) {
     if (b->d_wg_seg) (void)hipFree(b->d_wg_seg);
     if (b->d_flags) (void)hipFree(b->d_flags);
     if (b->d_err) (void)hipFree(b->d_err);
+    if (b->d_wave_inst) (void)hipFree(b->d_wave_inst);
     delete b;
     ctx->batch = nullptr;
 }
@@ -517,6 +636,22 @@ lbkm_status lbkm_batch_create(int32_t n_inst, const int32_t* nx, const lbkm_grid
         if (e == hipSuccess) e = hipMalloc((void**)&b->u[i], sizeof(double) * 2 * b->plane);
     }
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_inst, sizeof(BatchInst) * n_inst);
+    if (e == hipSuccess) {
+        // per 64-cell wave of the packed cells: the first and the last instance it overlaps
+        b->nwaves = (int)((total + 63) / 64);
+        std::vector<int32_t> wi(2 * (size_t)b->nwaves);
+        int k = 0;
+        for (int w = 0; w < b->nwaves; ++w) {
+            const int64_t a = 64 * (int64_t)w, z = std::min<int64_t>(a + 63, total - 1);
+            while (k + 1 < n_inst && a >= b->off[k + 1]) ++k;
+            int k1 = k;
+            while (k1 + 1 < n_inst && z >= b->off[k1 + 1]) ++k1;
+            wi[2 * (size_t)w] = k;
+            wi[2 * (size_t)w + 1] = k1;
+        }
+        e = hipMalloc((void**)&b->d_wave_inst, sizeof(int32_t) * wi.size());
+        if (e == hipSuccess) e = hipMemcpy(b->d_wave_inst, wi.data(), sizeof(int32_t) * wi.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_err, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(int32_t));
     if (e != hipSuccess) return hip_fail(ctx, e, "batch allocation");
@@ -542,6 +677,8 @@ lbkm_status lbkm_batch_set_params(lbkm_ctx* ctx, const double* S, const double* 
         I.a8c = ck.a8c;
         I.a9c = ck.a9c;
         I.amod = ck.amod;
+        I.lo = b->off[k];
+        I.hi = b->off[k] + b->nx[k] - 1;
         any_amod |= ck.amod != 0;
     }
     ctx->h = trial;
@@ -594,7 +731,7 @@ lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg) {
     if (e == hipSuccess) e = hipEventCreate(&t1);
     int best = b->wgs_per_cu;
     float best_ms = 1e30f;
-    const int cands[] = {1, 2, 3, 4, 6, 8};
+    const int cands[] = {0, 1, 2, 3, 4, 6, 8};          // 0: one launch per step
     for (int cand : cands) {
         if (e != hipSuccess) break;
         st = build_decomposition(ctx, cand);
@@ -640,7 +777,7 @@ lbkm_status lbkm_batch_autotune(lbkm_ctx* ctx, int32_t* cells_per_wg) {
 lbkm_status lbkm_batch_set_launch(lbkm_ctx* ctx, int32_t wgs_per_cu) {
     lbkm_status st = batch_ready(ctx, false);
     if (st != LBKM_OK) return st;
-    if (wgs_per_cu < 1 || wgs_per_cu > 16) return fail(ctx, LBKM_EINVAL, "wgs_per_cu must be in 1..16");
+    if (wgs_per_cu < 0 || wgs_per_cu > 16) return fail(ctx, LBKM_EINVAL, "wgs_per_cu must be in 0..16");
     st = build_decomposition(ctx, wgs_per_cu);
     if (st != LBKM_OK) return st;
     if (ctx->batch->wgs_per_cu != wgs_per_cu)

@@ -433,13 +433,15 @@ class Batch:
         return v.value
 
     def set_launch(self, wgs_per_cu: int):
+        """0: one launch per step; 1..16: the persistent kernel at that many work-groups per CU."""
         self._call("lbkm_batch_set_launch", ctypes.c_int32(int(wgs_per_cu)))
 
     def step(self, n: int = 1):
         self._call("lbkm_batch_step", ctypes.c_int64(int(n)))
 
     def status(self):
-        """(work-groups, work-groups per CU); raises if a neighbour wait ran out."""
+        """(work-groups per launch, work-groups per CU or 0 with one launch per step); raises
+        if a neighbour wait ran out."""
         a, b = ctypes.c_int32(), ctypes.c_int32()
         self._call("lbkm_batch_status", ctypes.byref(a), ctypes.byref(b))
         return a.value, b.value

@@ -1,8 +1,8 @@
 """Batched 1D path (a ragged batch of independent detonation tubes advanced by one
-persistent launch per lbkm_batch_step call): parity with the CPU oracle instance by
-instance (max relative error <= 1e-10, same metric as the single-grid tests), agreement
-with the single-grid path, and invariance under the launch shape, the autotuner and the
-way the steps are chunked.
+persistent launch per lbkm_batch_step call, or by one launch per step): parity with the CPU
+oracle instance by instance (max relative error <= 1e-10, same metric as the single-grid
+tests), agreement with the single-grid path, and invariance under the launch mode and
+shape, the autotuner and the way the steps are chunked.
 """
 
 import numpy as np
@@ -78,15 +78,36 @@ def _max_rel_diff(a, b):
     return worst
 
 
-def test_ragged_edge_batch_matches_oracle_per_instance():
+@pytest.mark.parametrize("wgs_per_cu", [2, 0])
+def test_ragged_edge_batch_matches_oracle_per_instance(wgs_per_cu):
+    """Persistent kernel (2 work-groups per CU) and one launch per step (0)."""
     spec = _edge_spec()
     b = _lbkm().batch_from_spec(spec)
+    b.set_launch(wgs_per_cu)
     b.step(120)
     b.step(180)
     print("launch shape (wgs, wgs/CU):", b.status(), flush=True)
     per = _split(b, _moments(b))
     for k in range(len(spec.nx)):
         _assert_parity_with_oracle(spec, k, per[k], 300, "edge batch")
+
+
+def test_launch_per_step_gives_the_persistent_kernels_bits():
+    """One launch per step (graphs of 64 launches and a remainder) against the persistent
+    kernel at 1 and 2 work-groups per CU: the same cells, bit for bit, including waves that
+    hold several short instances and calls whose step counts cross the 64-step chunks."""
+    spec = _edge_spec()
+    runs = {}
+    for mode in (0, 1, 2):
+        b = _lbkm().batch_from_spec(spec)
+        b.set_launch(mode)
+        for n in (77, 53, 64, 1):
+            b.step(n)
+        assert b.status()[1] == mode
+        runs[mode] = _moments(b)
+    for mode in (1, 2):
+        for q in ("rho", "ux", "uy", "T", "lam"):
+            assert np.array_equal(runs[0][q], runs[mode][q]), (mode, q)
 
 
 def test_batch_refuses_the_srt_switch_and_runge_kutta():
@@ -154,10 +175,11 @@ def test_full_size_batch_sampled_instances():
         assert d <= SAME_TOL, (k, d)
 
 
-def test_batch_with_rate_exponents_and_without_modification():
-    """Two more specialisations of the persistent kernel: rate exponents m = 2, n = 0.5, and
-    a batch whose instances all have Pr = 1 (A_hat off); both against the single-grid path
-    and the shortest instance against the oracle."""
+@pytest.mark.parametrize("wgs_per_cu", [2, 0])
+def test_batch_with_rate_exponents_and_without_modification(wgs_per_cu):
+    """Two more specialisations of the batch kernels (persistent, and one launch per step):
+    rate exponents m = 2, n = 0.5, and a batch whose instances all have Pr = 1 (A_hat off);
+    both against the single-grid path and the shortest instance against the oracle."""
     for tweak in ("exponents", "pr1"):
         s = W.batched(n_inst=6, nx_lo=20, nx_hi=700, seed=23)
         if tweak == "exponents":
@@ -168,8 +190,9 @@ def test_batch_with_rate_exponents_and_without_modification():
             R[:, 8] = R[:, 6]
             spec = W.BatchSpec(nx=s.nx, R=R, Pr=np.ones(len(s.nx)), base=s.base)
         b = _lbkm().batch_from_spec(spec)
+        b.set_launch(wgs_per_cu)
         b.step(150)
-        b.status()
+        assert b.status()[1] == wgs_per_cu
         per = _split(b, _moments(b))
         k0 = int(np.argmin(spec.nx))
         _assert_parity_with_oracle(spec, k0, per[k0], 150, "batch " + tweak)
