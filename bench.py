@@ -175,16 +175,21 @@ def cpu_baseline(w, tile=1024, steps=8):
                                  f"{dt1:.1f} s"}
 
 
-def bench_batched(ns_per_cell_plain, steps=5000, chunk=500):
+def bench_batched(ns_per_cell_plain, steps=5000, chunk=500, launch=None):
     """Config of 128 ragged 1D detonations: autotune (one launch per step, or the persistent
     kernel at 1-8 work-groups per CU), then `steps` steps in calls of `chunk` steps each
-    (each call replays captured graphs)."""
+    (each call replays captured graphs).  `launch` fixes the mode instead (0: one launch per
+    step, 1..8: persistent at that many work-groups per CU)."""
     import torch
     from paper_1411_6697_amd import lbkm
     from paper_1411_6697_amd import workloads as W
     spec = W.batched(steps=steps)
     b = lbkm.batch_from_spec(spec)
-    cells_per_wg = b.autotune()
+    if launch is None:
+        cells_per_wg = b.autotune()
+    else:
+        b.set_launch(launch)
+        cells_per_wg = -(-b.total // b.status()[0])
     b.step(chunk)                                  # captures the replayed graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -395,6 +400,9 @@ def main():
                          "(l = LDS-staged stencil, s = stream-first kernel, h = centre values shared in LDS, ORDER 1 = "
                          "column bands); used to "
                          "profile a stated shape")
+    ap.add_argument("--batch-launch", type=int, default=None,
+                    help="fix the batched run's launch instead of autotuning it: 0 = one launch per step, "
+                         "1..8 = the persistent kernel at that many work-groups per CU")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -510,7 +518,7 @@ def main():
     }
     ns_cell = ms * 1e6 / cells
     if not args.no_batched:
-        out["batched"] = bench_batched(ns_cell)
+        out["batched"] = bench_batched(ns_cell, launch=args.batch_launch)
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(ns_cell)
